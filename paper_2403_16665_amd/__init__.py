@@ -1,0 +1,187 @@
+"""MI355X (gfx950) alpha-dense DFT -- Python binding of the C ABI in include/dense_dft.h.
+
+The transform (paper Section 2, eq. (7) on the grid of eq. (6), T/N factor of
+eq. (2)):  X_m = (T/N) sum_{n<N} x_n exp(-2 pi i m n / (alpha N)),
+m < alpha N, computed on the GPU in the FFT-structured form of Section 3.
+
+This module only marshals arguments: it passes device pointers taken from
+torch tensors and the current HIP stream to ``libdensedft.so``; every step of
+the transform runs in the library's HIP kernels.  Importing it fails loudly
+when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdensedft.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first "
+        "(python -c 'import __graft_entry__ as g; g.build()')")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+DD_F32, DD_C64, DD_F64, DD_C128 = 0, 1, 2, 3
+DD_TWIDDLE_FP64, DD_TWIDDLE_FP32 = 0, 1
+STATUS = {0: "DD_OK", 1: "DD_ERR_INVALID", 2: "DD_ERR_UNSUPPORTED", 3: "DD_ERR_NOMEM",
+          4: "DD_ERR_DEVICE", 5: "DD_ERR_BUSY", 6: "DD_ERR_TOO_LARGE", 7: "DD_ERR_TIMEOUT",
+          8: "DD_ERR_CLOSED"}
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_lib.dense_dft_plan.argtypes = [ctypes.POINTER(_vp), _i64, ctypes.c_int32, ctypes.c_double, _i64,
+                                ctypes.c_int, ctypes.c_uint32]
+_lib.dense_dft_plan.restype = ctypes.c_int
+_lib.dense_dft_exec.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.dense_dft_exec.restype = ctypes.c_int
+_lib.dense_dft_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+_lib.dense_dft_workspace_size.restype = ctypes.c_int
+_lib.dense_dft_destroy.argtypes = [_vp]
+_lib.dense_dft_destroy.restype = ctypes.c_int
+_lib.dense_dft_plan_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_i64),
+                                     ctypes.POINTER(_i64)]
+_lib.dense_dft_plan_info.restype = ctypes.c_int
+_lib.dense_dft_profile_begin.argtypes = [_vp, ctypes.c_int32]
+_lib.dense_dft_profile_begin.restype = ctypes.c_int
+_lib.dense_dft_profile_end.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+_lib.dense_dft_profile_end.restype = ctypes.c_int
+_lib.dense_dft_status_string.argtypes = [ctypes.c_int]
+_lib.dense_dft_status_string.restype = ctypes.c_char_p
+_lib.dense_dft_version.argtypes = []
+_lib.dense_dft_version.restype = ctypes.c_int32
+
+
+class DenseDFTError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)} "
+                         f"({_lib.dense_dft_status_string(status).decode()})")
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise DenseDFTError(rc, what)
+
+
+def dense_dft_status_string(status: int) -> str:
+    return _lib.dense_dft_status_string(int(status)).decode()
+
+
+def dense_dft_version() -> int:
+    return int(_lib.dense_dft_version())
+
+
+class Plan:
+    """Owning handle of a dd_plan_t; destroyed when garbage-collected."""
+
+    def __init__(self, handle, N, alpha, T, batch, dtype, flags):
+        self.handle = handle
+        self.N, self.alpha, self.T, self.batch = N, alpha, T, batch
+        self.dtype, self.flags = dtype, flags
+
+    @property
+    def M(self) -> int:
+        return self.alpha * self.N
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.dense_dft_destroy(h)
+            self.handle = None
+
+
+def dense_dft_plan(N: int, alpha: int, T: float, batch: int, dtype: int,
+                   flags: int = DD_TWIDDLE_FP64) -> Plan:
+    h = _vp()
+    _check(_lib.dense_dft_plan(ctypes.byref(h), int(N), int(alpha), float(T), int(batch),
+                               int(dtype), int(flags)), "dense_dft_plan")
+    return Plan(h, int(N), int(alpha), float(T), int(batch), int(dtype), int(flags))
+
+
+def dense_dft_workspace_size(plan: Plan) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.dense_dft_workspace_size(plan.handle, ctypes.byref(n)), "dense_dft_workspace_size")
+    return int(n.value)
+
+
+def dense_dft_plan_info(plan: Plan):
+    """(passes, N1, N2) of the schedule the plan chose."""
+    p, n1, n2 = ctypes.c_int32(), _i64(), _i64()
+    _check(_lib.dense_dft_plan_info(plan.handle, ctypes.byref(p), ctypes.byref(n1),
+                                    ctypes.byref(n2)), "dense_dft_plan_info")
+    return int(p.value), int(n1.value), int(n2.value)
+
+
+def _ptr(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def dense_dft_exec(plan: Plan, x, X, workspace=None, stream=None) -> None:
+    """Enqueue the plan on ``stream`` (default: torch's current stream).
+
+    x: device tensor [batch, N] of the plan's dtype; X: device complex tensor
+    [batch, alpha*N]; workspace: optional device tensor of at least
+    dense_dft_workspace_size(plan) bytes.
+    """
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+    _check(_lib.dense_dft_exec(plan.handle, _ptr(x), _ptr(X), _ptr(workspace), _vp(stream)),
+           "dense_dft_exec")
+
+
+KERNEL_KINDS = {1: "single", 2: "pass1", 3: "pass2"}
+
+
+def dense_dft_profile_begin(plan: Plan, max_launches: int) -> None:
+    _check(_lib.dense_dft_profile_begin(plan.handle, int(max_launches)), "dense_dft_profile_begin")
+
+
+def dense_dft_profile_end(plan: Plan, cap: int = 4096):
+    """List of (kind, milliseconds) for each launch recorded since profile_begin."""
+    kinds = (ctypes.c_int32 * cap)()
+    ms = (ctypes.c_float * cap)()
+    n = ctypes.c_int32()
+    _check(_lib.dense_dft_profile_end(plan.handle, kinds, ms, int(cap), ctypes.byref(n)),
+           "dense_dft_profile_end")
+    return [(KERNEL_KINDS.get(kinds[i], str(kinds[i])), float(ms[i])) for i in range(n.value)]
+
+
+def dense_dft_destroy(plan: Plan) -> None:
+    if plan.handle:
+        _check(_lib.dense_dft_destroy(plan.handle), "dense_dft_destroy")
+        plan.handle = None
+
+
+# --- torch conveniences (memory allocation only) ---
+def dtype_code(torch_dtype) -> int:
+    import torch
+    m = {torch.float32: DD_F32, torch.complex64: DD_C64, torch.float64: DD_F64,
+         torch.complex128: DD_C128}
+    if torch_dtype not in m:
+        raise TypeError(f"unsupported input dtype {torch_dtype}")
+    return m[torch_dtype]
+
+
+def out_dtype(code: int):
+    import torch
+    return torch.complex64 if code in (DD_F32, DD_C64) else torch.complex128
+
+
+def alpha_dft(x, alpha: int, T: float, flags: int = DD_TWIDDLE_FP64, plan: Plan | None = None):
+    """X = alpha-dense DFT of the rows of device tensor x ([batch, N] or [N])."""
+    import torch
+    squeeze = x.dim() == 1
+    x2 = x.reshape(1, -1) if squeeze else x
+    x2 = x2.contiguous()
+    batch, N = x2.shape
+    code = dtype_code(x2.dtype)
+    if plan is None:
+        plan = dense_dft_plan(N, alpha, T, batch, code, flags)
+    X = torch.empty((batch, alpha * N), dtype=out_dtype(code), device=x2.device)
+    dense_dft_exec(plan, x2, X)
+    return X[0] if squeeze else X

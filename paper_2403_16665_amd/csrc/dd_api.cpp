@@ -1,0 +1,462 @@
+// dd_api.cpp -- planner and C ABI of the alpha-dense DFT library (host code).
+//
+// A plan fixes N, alpha, T, batch and dtype (the problem as the paper states
+// it, Section 2: N samples over [0, T], alpha*N bins spaced 1/(alpha T)),
+// chooses the schedule, and owns the device twiddle tables.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/dense_dft.h"
+#include "dd_launch.hpp"
+
+using namespace dd;
+
+struct dd_plan {
+  int device = 0;
+  int64_t N = 0, N1 = 0, N2 = 1, batch = 0;
+  int alpha = 1;
+  double T = 1.0;
+  dd_dtype dtype = DD_C64;
+  uint32_t flags = 0;
+  bool dbl = false;
+  int in_bytes = 8, rbytes = 4;
+  int passes = 1;
+  // single pass
+  int s_lines = 1, s_TL = 1;
+  size_t s_lds = 0;
+  // two passes
+  int p1_lines = 1, p1_TL = 1, p1_ntile = 1, p1_jgroup = 1, p1_njg = 1;
+  size_t p1_lds = 0;
+  int p2_lines = 1, p2_TL = 1, p2_ntile = 1;
+  size_t p2_lds = 0;
+  int64_t chunk = 1;
+  // device tables (element type cx<float> or cx<double>)
+  void* twL1 = nullptr;   // stage twiddles of the N1 (or N) line FFT
+  void* twL2 = nullptr;   // stage twiddles of the N2 line FFT
+  void* twPre = nullptr;  // [j][n1] W_{alpha N1}^{j n1}
+  void* twQ = nullptr;    // [j][n2] W_{alpha N}^{j n2}
+  void* twPost = nullptr; // [k1][n2] W_N^{k1 n2}
+  void* ws = nullptr;     // default workspace
+  size_t ws_bytes = 0;
+  // per-launch event timing (dense_dft_profile_begin / _end)
+  bool prof_on = false;
+  int prof_n = 0;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_kind;
+};
+
+namespace {
+
+bool is_smooth(int64_t n) {
+  if (n < 1) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  while (n % 5 == 0) n /= 5;
+  return n == 1;
+}
+
+int ilog2(int64_t v) {
+  int r = 0;
+  while ((int64_t)1 << (r + 1) <= v) ++r;
+  return r;
+}
+
+size_t cx_bytes(const dd_plan* p) { return (size_t)2 * p->rbytes; }
+
+dd_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return DD_OK;
+  if (e == hipErrorOutOfMemory) return DD_ERR_NOMEM;
+  return DD_ERR_DEVICE;
+}
+
+void free_events(dd_plan* p) {
+  for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
+  p->prof_ev.clear();
+  p->prof_kind.clear();
+  p->prof_on = false;
+  p->prof_n = 0;
+}
+
+// Launch wrapper: brackets the launch with events while profiling is on.
+template <typename F>
+hipError_t timed_launch(dd_plan* p, int kind, hipStream_t s, F&& launch) {
+  const bool rec = p->prof_on && p->prof_n < (int)p->prof_kind.size();
+  if (rec) {
+    hipError_t e = hipEventRecord(p->prof_ev[2 * p->prof_n], s);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) return e;
+  if (rec) {
+    e = hipEventRecord(p->prof_ev[2 * p->prof_n + 1], s);
+    p->prof_kind[p->prof_n] = kind;
+    ++p->prof_n;
+  }
+  return e;
+}
+
+void free_tables(dd_plan* p) {
+  void** bufs[] = {&p->twL1, &p->twL2, &p->twPre, &p->twQ, &p->twPost, &p->ws};
+  for (void** b : bufs) {
+    if (*b) (void)hipFree(*b);
+    *b = nullptr;
+  }
+}
+
+// Stage twiddle table of a line plan: for each stage st >= 1 the block
+// [s][k] = W_{NS RAD}^{k s} (s < RAD, k < NS).
+dd_status gen_stage_table(dd_plan* p, void** out, int L, bool fp32, hipStream_t s) {
+  LinePlan lp = make_line_plan(L);
+  const int n = line_tw_size(lp);
+  const size_t bytes = (size_t)(n > 0 ? n : 1) * cx_bytes(p);
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) return hip_status(e);
+  for (int st = 1; st < lp.nst; ++st) {
+    const int NS = line_ns(lp, st), RAD = lp.rad[st];
+    const int off = line_tw_offset(lp, st);
+    if (p->dbl)
+      e = launch_twiddle(static_cast<cx<double>*>(*out) + off, RAD, NS, 0, (int64_t)NS * RAD, 0, s);
+    else
+      e = launch_twiddle(static_cast<cx<float>*>(*out) + off, RAD, NS, 0, (int64_t)NS * RAD, fp32, s);
+    if (e != hipSuccess) return hip_status(e);
+  }
+  return DD_OK;
+}
+
+// out[r][c] = W_den^{(r c) mod den}
+dd_status gen_table(dd_plan* p, void** out, int64_t rows, int64_t cols, int64_t den, bool fp32,
+                    hipStream_t s) {
+  hipError_t e = hipMalloc(out, (size_t)(rows * cols) * cx_bytes(p));
+  if (e != hipSuccess) return hip_status(e);
+  if (p->dbl)
+    e = launch_twiddle(static_cast<cx<double>*>(*out), rows, cols, 0, den, 0, s);
+  else
+    e = launch_twiddle(static_cast<cx<float>*>(*out), rows, cols, 0, den, fp32, s);
+  return hip_status(e);
+}
+
+// Choose N = N1 * N2 for the two-pass schedule: N1 any instantiated length,
+// N2 a power of two >= 2, as balanced as possible (N1 <= N2 on ties).
+bool factor_two_pass(int64_t N, int rbytes, int64_t* N1, int64_t* N2) {
+  int best = 1 << 30;
+  bool found = false;
+  for (int64_t n2 = 2; n2 <= 4096; n2 *= 2) {
+    if (N % n2) continue;
+    const int64_t n1 = N / n2;
+    if (n1 > 4096 || !len_supported((int)n1) || !pass2_len_supported((int)n2)) continue;
+    int score = std::abs(ilog2(n1) - ilog2(n2)) * 2 + (n1 > n2 ? 1 : 0);
+    if (n2 < 16) score += 8;  // narrow column tiles store short runs
+    if (n2 % geom_pass((int)n1, rbytes).lines != 0) score += 4;  // idle columns in pass 1
+    if (score < best) {
+      best = score;
+      *N1 = n1;
+      *N2 = n2;
+      found = true;
+    }
+  }
+  return found;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dense_dft_status_string(dd_status s) {
+  switch (s) {
+    case DD_OK: return "ok";
+    case DD_ERR_INVALID: return "invalid argument";
+    case DD_ERR_UNSUPPORTED: return "unsupported size or parameter";
+    case DD_ERR_NOMEM: return "out of memory";
+    case DD_ERR_DEVICE: return "device error";
+    case DD_ERR_BUSY: return "busy";
+    case DD_ERR_TOO_LARGE: return "request exceeds the memory budget";
+    case DD_ERR_TIMEOUT: return "timed out";
+    case DD_ERR_CLOSED: return "closed";
+  }
+  return "unknown status";
+}
+
+int32_t dense_dft_version(void) { return 100; }
+
+dd_status dense_dft_plan(dd_plan_t* out, int64_t N, int32_t alpha, double T, int64_t batch, dd_dtype dtype,
+                         uint32_t flags) {
+  if (!out) return DD_ERR_INVALID;
+  *out = nullptr;
+  if (N < 1 || batch < 1 || !(T > 0.0) || !std::isfinite(T)) return DD_ERR_INVALID;
+  if (dtype != DD_F32 && dtype != DD_C64 && dtype != DD_F64 && dtype != DD_C128) return DD_ERR_INVALID;
+  if (flags & ~(uint32_t)DD_TWIDDLE_FP32) return DD_ERR_INVALID;
+  if (alpha < 1) return DD_ERR_UNSUPPORTED;
+  const int64_t M = (int64_t)alpha * N;
+  if (M > ((int64_t)1 << 31) || batch > INT64_MAX / M) return DD_ERR_UNSUPPORTED;
+  if (!is_smooth(N)) return DD_ERR_UNSUPPORTED;
+
+  dd_plan* p = new (std::nothrow) dd_plan;
+  if (!p) return DD_ERR_NOMEM;
+  p->N = N;
+  p->alpha = alpha;
+  p->T = T;
+  p->batch = batch;
+  p->dtype = dtype;
+  p->flags = flags;
+  p->dbl = dtype == DD_F64 || dtype == DD_C128;
+  p->rbytes = p->dbl ? 8 : 4;
+  p->in_bytes = dtype == DD_F32 ? 4 : dtype == DD_C128 ? 16 : 8;
+  const bool fp32tw = !p->dbl && (flags & DD_TWIDDLE_FP32);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return DD_ERR_DEVICE;
+  }
+
+  // Schedule.  One pass when the alpha*N spectrum of a signal fits the LDS
+  // image of one block; otherwise two passes.
+  const size_t single_budget = 150 * 1024;
+  bool single = false;
+  if (N <= 4096 && len_supported((int)N)) {
+    KGeom g = geom_single((int)N, p->rbytes);
+    size_t per_line = lds_single((int)N, 1, alpha, p->rbytes);
+    if (per_line <= single_budget) {
+      single = true;
+      int lines = g.lines;
+      while (lines > 1 && (size_t)lines * per_line > single_budget) lines /= 2;
+      if (lines > batch) lines = (int)batch;
+      p->s_lines = lines < 1 ? 1 : lines;
+      p->s_TL = g.TL;
+      p->s_lds = lds_single((int)N, p->s_lines, alpha, p->rbytes);
+    }
+  }
+  if (single) {
+    p->passes = 1;
+    p->N1 = N;
+    p->N2 = 1;
+  } else {
+    int64_t N1 = 0, N2 = 0;
+    if (!factor_two_pass(N, p->rbytes, &N1, &N2)) {
+      delete p;
+      return DD_ERR_UNSUPPORTED;
+    }
+    p->passes = 2;
+    p->N1 = N1;
+    p->N2 = N2;
+    KGeom g1 = geom_pass((int)N1, p->rbytes);
+    KGeom g2 = geom_pass((int)N2, p->rbytes);
+    p->p1_lines = g1.lines;  // compile-time column count of the kernel
+    p->p1_TL = g1.TL;
+    p->p1_ntile = (int)((N2 + g1.lines - 1) / g1.lines);
+    p->p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes);
+    p->p2_lines = g2.lines;
+    p->p2_TL = g2.TL;
+    p->p2_ntile = (int)((alpha * N1 + g2.lines - 1) / g2.lines);
+    p->p2_lds = lds_pass2((int)N2, g2.lines, p->rbytes);
+    // Signals per pass pair: keep the scratch of one chunk within 128 MiB.
+    const size_t per_sig = (size_t)M * cx_bytes(p);
+    int64_t chunk = (int64_t)((128u << 20) / per_sig);
+    if (chunk < 1) chunk = 1;
+    if (chunk > batch) chunk = batch;
+    if (const char* ev = std::getenv("DD_TUNE_CHUNK")) {
+      long v = std::atol(ev);
+      if (v >= 1) chunk = v < batch ? v : batch;
+    }
+    p->chunk = chunk;
+    // j values per pass-1 block: all alpha (x and the post-twiddles are read
+    // once per block) unless that leaves fewer than two blocks per CU.
+    int jg = alpha;
+    while (jg > 1 && chunk * p->p1_ntile * ((alpha + jg - 1) / jg) < 512) jg = (jg + 1) / 2;
+    if (const char* ev = std::getenv("DD_TUNE_JGROUP")) {
+      long v = std::atol(ev);
+      if (v >= 1 && v <= alpha) jg = (int)v;
+    }
+    p->p1_jgroup = jg;
+    p->p1_njg = (alpha + jg - 1) / jg;
+    p->ws_bytes = (size_t)chunk * per_sig;
+  }
+
+  // Device tables, generated on the GPU (FP64 unless the FP32 variant).
+  hipStream_t s = nullptr;
+  dd_status st = DD_OK;
+  st = gen_stage_table(p, &p->twL1, (int)p->N1, fp32tw, s);
+  if (st == DD_OK) st = gen_table(p, &p->twPre, alpha, p->N1, (int64_t)alpha * p->N1, fp32tw, s);
+  if (st == DD_OK && p->passes == 2) {
+    st = gen_stage_table(p, &p->twL2, (int)p->N2, fp32tw, s);
+    if (st == DD_OK) st = gen_table(p, &p->twQ, alpha, p->N2, M, fp32tw, s);
+    if (st == DD_OK) st = gen_table(p, &p->twPost, p->N1, p->N2, N, fp32tw, s);
+    if (st == DD_OK) st = hip_status(hipMalloc(&p->ws, p->ws_bytes));
+  }
+  if (st == DD_OK) st = hip_status(hipStreamSynchronize(s));
+  if (st != DD_OK) {
+    free_tables(p);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return DD_OK;
+}
+
+dd_status dense_dft_workspace_size(dd_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return DD_ERR_INVALID;
+  *bytes = p->ws_bytes;
+  return DD_OK;
+}
+
+dd_status dense_dft_plan_info(dd_plan_t p, int32_t* passes, int64_t* N1, int64_t* N2) {
+  if (!p) return DD_ERR_INVALID;
+  if (passes) *passes = p->passes;
+  if (N1) *N1 = p->N1;
+  if (N2) *N2 = p->N2;
+  return DD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename R, typename In>
+dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s) {
+  const R scale = (R)(p->T / (double)p->N);
+  const int64_t M = (int64_t)p->alpha * p->N;
+  if (p->passes == 1) {
+    DenseArgs<R> a{};
+    a.batch = p->batch;
+    a.x_stride = p->N;
+    a.y_stride = M;
+    a.N1 = (int)p->N;
+    a.N2 = 1;
+    a.alpha = p->alpha;
+    a.lines = p->s_lines;
+    a.scale = scale;
+    a.twL = static_cast<const cx<R>*>(p->twL1);
+    a.twPre = static_cast<const cx<R>*>(p->twPre);
+    LaunchCfg c{(p->batch + p->s_lines - 1) / p->s_lines, p->s_lines * p->s_TL, p->s_lds, s};
+    return hip_status(timed_launch(p, 1, s, [&] { return launch_single((int)p->N, c, x, X, a); }));
+  }
+  for (int64_t c0 = 0; c0 < p->batch; c0 += p->chunk) {
+    const int64_t nb = p->batch - c0 < p->chunk ? p->batch - c0 : p->chunk;
+    DenseArgs<R> a1{};
+    a1.batch = nb;
+    a1.x_stride = p->N;
+    a1.y_stride = M;
+    a1.N1 = (int)p->N1;
+    a1.N2 = (int)p->N2;
+    a1.alpha = p->alpha;
+    a1.lines = p->p1_lines;
+    a1.ntile = p->p1_ntile;
+    a1.jgroup = p->p1_jgroup;
+    a1.njg = p->p1_njg;
+    a1.scale = scale;
+    a1.twL = static_cast<const cx<R>*>(p->twL1);
+    a1.twPre = static_cast<const cx<R>*>(p->twPre);
+    a1.twQ = static_cast<const cx<R>*>(p->twQ);
+    a1.twPost = static_cast<const cx<R>*>(p->twPost);
+    LaunchCfg c1{nb * p->p1_ntile * p->p1_njg, p->p1_lines * p->p1_TL, p->p1_lds, s};
+    hipError_t e = timed_launch(p, 2, s, [&] { return launch_pass1((int)p->N1, c1, x + c0 * p->N, ws, a1); });
+    if (e != hipSuccess) return hip_status(e);
+    DenseArgs<R> a2 = a1;
+    a2.lines = p->p2_lines;
+    a2.ntile = p->p2_ntile;
+    a2.twL = static_cast<const cx<R>*>(p->twL2);
+    LaunchCfg c2{nb * p->p2_ntile, p->p2_lines * p->p2_TL, p->p2_lds, s};
+    e = timed_launch(p, 3, s, [&] { return launch_pass2((int)p->N2, c2, ws, X + c0 * M, a2); });
+    if (e != hipSuccess) return hip_status(e);
+  }
+  return DD_OK;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+dd_status dense_dft_exec(dd_plan_t p, const void* x, void* X, void* workspace, void* stream) {
+  if (!p || !x || !X) return DD_ERR_INVALID;
+  const size_t out_cx = cx_bytes(p);
+  const size_t in_align = p->in_bytes;
+  if ((uintptr_t)x % in_align != 0 || (uintptr_t)X % out_cx != 0) return DD_ERR_INVALID;
+  const size_t in_total = (size_t)p->batch * p->N * p->in_bytes;
+  const size_t out_total = (size_t)p->batch * p->alpha * p->N * out_cx;
+  if (overlaps(x, in_total, X, out_total)) return DD_ERR_INVALID;
+  void* ws = workspace ? workspace : p->ws;
+  if (p->passes == 2) {
+    if (!ws || (uintptr_t)ws % out_cx != 0) return DD_ERR_INVALID;
+    if (overlaps(ws, p->ws_bytes, X, out_total) || overlaps(ws, p->ws_bytes, x, in_total))
+      return DD_ERR_INVALID;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  switch (p->dtype) {
+    case DD_F32:
+      return exec_typed<float>(p, static_cast<const float*>(x), static_cast<cx<float>*>(X),
+                               static_cast<cx<float>*>(ws), s);
+    case DD_C64:
+      return exec_typed<float>(p, static_cast<const cx<float>*>(x), static_cast<cx<float>*>(X),
+                               static_cast<cx<float>*>(ws), s);
+    case DD_F64:
+      return exec_typed<double>(p, static_cast<const double*>(x), static_cast<cx<double>*>(X),
+                                static_cast<cx<double>*>(ws), s);
+    case DD_C128:
+      return exec_typed<double>(p, static_cast<const cx<double>*>(x), static_cast<cx<double>*>(X),
+                                static_cast<cx<double>*>(ws), s);
+  }
+  return DD_ERR_INVALID;
+}
+
+dd_status dense_dft_destroy(dd_plan_t p) {
+  if (!p) return DD_ERR_INVALID;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  free_events(p);
+  free_tables(p);
+  (void)hipSetDevice(cur);
+  delete p;
+  return DD_OK;
+}
+
+dd_status dense_dft_profile_begin(dd_plan_t p, int32_t max_launches) {
+  if (!p || max_launches < 1) return DD_ERR_INVALID;
+  free_events(p);
+  try {
+    p->prof_ev.resize(2 * (size_t)max_launches, nullptr);
+    p->prof_kind.assign((size_t)max_launches, 0);
+  } catch (...) {
+    free_events(p);
+    return DD_ERR_NOMEM;
+  }
+  for (auto& e : p->prof_ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      free_events(p);
+      return DD_ERR_DEVICE;
+    }
+  }
+  p->prof_n = 0;
+  p->prof_on = true;
+  return DD_OK;
+}
+
+dd_status dense_dft_profile_end(dd_plan_t p, int32_t* kinds, float* ms, int32_t cap, int32_t* count) {
+  if (!p || !count || (cap > 0 && (!kinds || !ms))) return DD_ERR_INVALID;
+  dd_status st = DD_OK;
+  const int n = p->prof_n;
+  if (n > 0 && hipEventSynchronize(p->prof_ev[2 * n - 1]) != hipSuccess) st = DD_ERR_DEVICE;
+  int w = 0;
+  for (int i = 0; st == DD_OK && i < n && w < cap; ++i, ++w) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, p->prof_ev[2 * i], p->prof_ev[2 * i + 1]) != hipSuccess) st = DD_ERR_DEVICE;
+    kinds[w] = p->prof_kind[i];
+    ms[w] = t;
+  }
+  *count = w;
+  free_events(p);
+  return st;
+}
+
+}  // extern "C"

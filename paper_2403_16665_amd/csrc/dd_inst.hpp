@@ -1,0 +1,54 @@
+// dd_inst.hpp -- instantiation bodies of the launchers; included by the
+// per-precision translation units with DD_R set to float or double.
+#pragma once
+
+#include "dd_launch.hpp"
+
+namespace dd {
+
+template <typename R, typename In>
+hipError_t launch_single_impl(int L, const LaunchCfg& c, const In* x, cx<R>* X, const DenseArgs<R>& a) {
+  switch (L) {
+#define DD_CASE(LL)                                                        \
+  case LL: {                                                               \
+    constexpr int B = Geom<LL, (int)sizeof(R)>::BLOCK_SINGLE;              \
+    return launch_kernel(k_single<R, In, LL, B>, c, x, X, a);              \
+  }
+    DD_ALL_LENGTHS(DD_CASE)
+#undef DD_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename R, typename In>
+hipError_t launch_pass1_impl(int L, const LaunchCfg& c, const In* x, cx<R>* Y, const DenseArgs<R>& a) {
+  switch (L) {
+#define DD_CASE(LL)                                                        \
+  case LL: {                                                               \
+    constexpr int C = Geom<LL, (int)sizeof(R)>::lines_pass();              \
+    return launch_kernel(k_pass1<R, In, LL, C>, c, x, Y, a);               \
+  }
+    DD_ALL_LENGTHS(DD_CASE)
+#undef DD_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename R>
+hipError_t launch_pass2_impl(int L, const LaunchCfg& c, const cx<R>* Y, cx<R>* X, const DenseArgs<R>& a) {
+  switch (L) {
+#define DD_CASE(LL)                                                        \
+  case LL: {                                                               \
+    constexpr int RB = Geom<LL, (int)sizeof(R)>::lines_pass();             \
+    return launch_kernel(k_pass2<R, LL, RB>, c, Y, X, a);                  \
+  }
+    DD_POW2_LENGTHS(DD_CASE)
+#undef DD_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dd

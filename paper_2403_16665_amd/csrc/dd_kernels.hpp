@@ -1,0 +1,260 @@
+// dd_kernels.hpp -- the alpha-dense DFT kernels for gfx950.
+//
+// Method (paper Section 3, eq. (9)-(13), unrolled): with m = alpha k + j,
+//   X_{alpha k + j} = (T/N) sum_n [x_n W_{alpha N}^{j n}] W_N^{k n},
+// i.e. alpha pre-twiddled length-N FFTs whose outputs interleave.  The
+// pre-twiddle is the first, pruned level of the paper's recursion: the level
+// whose inputs are one sample and (alpha-1) implied zeros (Section 4) is
+// just this multiply.
+//
+// Single pass (whole signal in one block): for each j, pre-twiddle, length-N
+// Stockham FFT in registers + LDS, write into an LDS image of the alpha*N
+// spectrum at alpha k + j; then one coalesced store of the whole spectrum.
+//
+// Two passes, N = N1 N2, n = N2 n1 + n2, m = m1 + alpha N1 k2 with
+// m1 = alpha k1 + j (the same identity applied to the four-step split):
+//   pass 1: for each column n2, the alpha-dense DFT of length N1 of
+//           x[N2 n1 + n2] (alpha pre-twiddled N1-point FFTs), times the
+//           inter-pass twiddle W_{alpha N}^{m1 n2} = W_N^{k1 n2} W_{alpha N}^{j n2}
+//           -> scratch Y[m1][n2]
+//   pass 2: for each row m1, the plain N2-point FFT over n2
+//           -> X[m1 + alpha N1 k2], stored as contiguous runs of rows.
+// Every twiddle exponent is an exact integer below its modulus.
+#pragma once
+
+#include "dd_fft.hpp"
+
+namespace dd {
+
+template <typename R>
+struct DenseArgs {
+  int64_t batch;      // signals handled by this launch
+  int64_t x_stride;   // input elements between signals
+  int64_t y_stride;   // complex elements between signals of the output / scratch
+  int N1, N2, alpha;
+  int lines;          // lines per block: signals (single), columns (pass 1), rows (pass 2)
+  int ntile;          // column tiles (pass 1) or row blocks (pass 2) per signal
+  int jgroup, njg;    // j values per block and number of j groups (pass 1)
+  R scale;            // T / N
+  const cx<R>* twL;   // stage twiddles of the line FFT of this kernel ([s][k] per stage)
+  const cx<R>* twPre; // W_{alpha N1}^{j n1}, laid out [j][n1]
+  const cx<R>* twQ;   // W_{alpha N}^{j n2}, laid out [j][n2]
+  const cx<R>* twPost;// W_N^{k1 n2}, laid out [k1][n2]
+};
+
+template <typename R> __device__ __forceinline__ cx<R> load_in(const float* p, int64_t i) { return {(R)p[i], (R)0}; }
+template <typename R> __device__ __forceinline__ cx<R> load_in(const double* p, int64_t i) { return {(R)p[i], (R)0}; }
+template <typename R> __device__ __forceinline__ cx<R> load_in(const cx<float>* p, int64_t i) { cx<float> v = p[i]; return {(R)v.re, (R)v.im}; }
+template <typename R> __device__ __forceinline__ cx<R> load_in(const cx<double>* p, int64_t i) { cx<double> v = p[i]; return {(R)v.re, (R)v.im}; }
+
+// Launch geometry shared by host and device: lines per block so that the
+// block has at most `max_threads` threads and its line data fits `lds_budget`.
+constexpr int LDS_BUDGET = 64 * 1024;
+
+constexpr int line_threads(int L) { return L / make_line_plan(L).EPT; }
+
+template <int L, int RBYTES>
+struct Geom {
+  static constexpr int TL = line_threads(L);
+  static constexpr int CX = 2 * RBYTES;
+  static constexpr int cap_lds(int lines) {
+    while (lines > 1 && lines * (L + L / 16 + 1) * CX > LDS_BUDGET) lines /= 2;
+    return lines;
+  }
+  // pass 1 / pass 2: aim for 16 lines, at most 1024 threads, LDS within budget
+  static constexpr int lines_pass() {
+    int l = 16;
+    if (TL * l < 256) l = 256 / TL;
+    while (l > 1 && TL * l > 1024) l /= 2;
+    return cap_lds(l);
+  }
+  static constexpr int BLOCK_PASS = TL * lines_pass();
+  // single pass: up to 256 threads (one line if TL >= 256)
+  static constexpr int lines_single() { return TL >= 256 ? 1 : 256 / TL; }
+  static constexpr int BLOCK_SINGLE = TL * lines_single();
+};
+
+// ---------------------------------------------------------------------------
+// Single pass: block = `lines` signals; thread t of line `line` owns samples
+// t + TL e.  Dynamic LDS: exchange (RowLayout) then the spectrum image.
+// ---------------------------------------------------------------------------
+template <typename R, typename In, int L, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_single(const In* __restrict__ x, cx<R>* __restrict__ X,
+                                                  DenseArgs<R> a) {
+  constexpr LinePlan P = make_line_plan(L);
+  constexpr int EPT = P.EPT;
+  constexpr int TL = L / EPT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* ex = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* img = ex + RowLayout<L>::elems(a.lines);
+  const int tid = threadIdx.x;
+  const int t = tid % TL, line = tid / TL;
+  const int64_t sig0 = (int64_t)blockIdx.x * a.lines;
+  const int64_t sig = sig0 + line;
+  const bool active = sig < a.batch;
+  const int M1 = a.alpha * L;
+
+  cx<R> xv[EPT];
+  if (active) {
+    const In* xs = x + sig * a.x_stride;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) xv[e] = cscale(load_in<R>(xs, t + TL * e), a.scale);
+  } else {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) xv[e] = {(R)0, (R)0};
+  }
+  const RowLayout<L> lay(line);
+  cx<R>* im = img + (int64_t)line * M1;
+  for (int j = 0; j < a.alpha; ++j) {
+    cx<R> v[EPT];
+    if (j == 0) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[e] = xv[e];
+    } else {
+      const cx<R>* __restrict__ pre = a.twPre + j * L + t;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pre[TL * e]);
+    }
+    line_fft<R, L>(v, t, ex, lay, a.twL);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) im[a.alpha * (t + TL * e) + j] = v[e];
+  }
+  __syncthreads();
+  const int64_t nl = min((int64_t)a.lines, a.batch - sig0);
+  const int64_t total = nl * M1;
+  cx<R>* dst = X + sig0 * a.y_stride;  // y_stride == alpha * L
+  for (int64_t i = tid; i < total; i += blockDim.x) dst[i] = img[i];
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1: block = (signal, tile of C columns n2, group of j values).  Thread
+// (c, t) with c fastest owns column n2 = tile*C + c, samples n1 = t + TL e.
+// ---------------------------------------------------------------------------
+template <typename R, typename In, int L, int C>
+__global__ __launch_bounds__(C * (L / make_line_plan(L).EPT)) void k_pass1(const In* __restrict__ x, cx<R>* __restrict__ Y,
+                                                 DenseArgs<R> a) {
+  constexpr LinePlan P = make_line_plan(L);
+  constexpr int EPT = P.EPT;
+  constexpr int TL = L / EPT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* ex = reinterpret_cast<cx<R>*>(smem_raw);
+  int64_t bid = blockIdx.x;
+  const int jg = (int)(bid % a.njg);
+  bid /= a.njg;
+  const int tile = (int)(bid % a.ntile);
+  const int64_t sig = bid / a.ntile;
+  const int tid = threadIdx.x;
+  const int c = tid % C, t = tid / C;
+  const int N2 = a.N2;
+  const int n2 = tile * C + c;
+  const ColLayout<C> lay(c);
+
+  const In* xs = x + sig * a.x_stride;
+  const bool colok = n2 < N2;  // a tile wider than N2 has idle columns
+  cx<R> xv[EPT], pw[EPT];
+  const unsigned in_off = (unsigned)(N2 * t + n2);          // lane part of N2 n1 + n2
+  const unsigned in_step = (unsigned)(N2 * TL);             // n1 -> n1 + TL
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    if (colok) {
+      xv[e] = cscale(load_in<R>(xs + in_step * e, in_off), a.scale);
+      pw[e] = (a.twPost + in_step * e)[in_off];             // W_N^{k1 n2}, k1 = t + TL e
+    } else {
+      xv[e] = {(R)0, (R)0};
+      pw[e] = {(R)0, (R)0};
+    }
+  }
+  const unsigned out_off = (unsigned)(a.alpha * N2 * t + n2);  // lane part of (alpha k1 + j) N2 + n2
+  const unsigned out_step = (unsigned)(a.alpha * N2 * TL);
+  cx<R>* ys = Y + sig * a.y_stride;
+  const int j0 = jg * a.jgroup;
+  const int j1 = min(a.alpha, j0 + a.jgroup);
+  for (int j = j0; j < j1; ++j) {
+    cx<R> v[EPT];
+    if (j == 0) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[e] = xv[e];
+    } else {
+      const cx<R>* __restrict__ pre = a.twPre + j * L + t;   // W_{alpha N1}^{j n1}
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pre[TL * e]);
+    }
+    line_fft<R, L>(v, t, ex, lay, a.twL);
+    if (colok) {
+      const cx<R> q = a.twQ[j * N2 + n2];  // W_{alpha N}^{j n2}
+      cx<R>* yj = ys + (int64_t)j * N2;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) (yj + out_step * e)[out_off] = cmul(v[e], cmul(pw[e], q));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2: block = (signal, block of R consecutive rows m1).  Thread (t, r)
+// with t fastest owns row m1 = block*R + r, elements n2 = t + TL e.  Output
+// X[m1 + alpha N1 k2] is staged in LDS and written as runs of R bins.
+// ---------------------------------------------------------------------------
+template <typename R, int L, int RB>
+__global__ __launch_bounds__(RB * (L / make_line_plan(L).EPT)) void k_pass2(const cx<R>* __restrict__ Y, cx<R>* __restrict__ X,
+                                                 DenseArgs<R> a) {
+  constexpr LinePlan P = make_line_plan(L);
+  constexpr int EPT = P.EPT;
+  constexpr int TL = L / EPT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* ex = reinterpret_cast<cx<R>*>(smem_raw);
+  const int64_t bid = blockIdx.x;
+  const int rb = (int)(bid % a.ntile);
+  const int64_t sig = bid / a.ntile;
+  const int tid = threadIdx.x;
+  const int t = tid % TL, r = tid / TL;
+  const int rows = a.alpha * a.N1;
+  const int m1 = rb * RB + r;
+  const bool ok = m1 < rows;
+  const cx<R>* ys = Y + sig * a.y_stride + (int64_t)rb * RB * L;
+  const unsigned row_off = (unsigned)(r * L + t);
+  cx<R> v[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) v[e] = ok ? (ys + TL * e)[row_off] : cx<R>{(R)0, (R)0};
+  const RowLayout<L> lay(r);
+  line_fft<R, L>(v, t, ex, lay, a.twL);
+  __syncthreads();
+  constexpr int SR = RB + 1;  // staging row stride (odd, spreads banks)
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) ex[(t + TL * e) * SR + r] = v[e];
+  __syncthreads();
+  cx<R>* xs = X + sig * a.y_stride;
+  constexpr int total = RB * L;
+  constexpr int NT = RB * TL;
+#pragma unroll 4
+  for (int i = tid; i < total; i += NT) {
+    const int rr = i % RB, k2 = i / RB;
+    const int m = rb * RB + rr;
+    if (m < rows) xs[(int64_t)m + (int64_t)rows * k2] = ex[k2 * SR + rr];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Twiddle tables: out[r][c] = W_den^{((r + r0) c) mod den}, exponent reduced
+// exactly in 64-bit integers, then sin/cos in FP64 (rounded once to R) or,
+// for the FP32 variant, angle and sin/cos in FP32 from the same exact q.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_twiddle(cx<R>* __restrict__ out, int64_t rows, int64_t cols, int64_t r0,
+                          int64_t den, int fp32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * cols) return;
+  const uint64_t r = (uint64_t)(i / cols + r0), c = (uint64_t)(i % cols);
+  const uint64_t q = (r * c) % (uint64_t)den;
+  if (fp32) {
+    float s, co;
+    const float ang = (float)q * (float)(6.283185307179586476925286766559 / (double)den);
+    sincosf(ang, &s, &co);
+    out[i] = {(R)co, (R)(-s)};
+  } else {
+    double s, co;
+    sincospi(2.0 * (double)q / (double)den, &s, &co);
+    out[i] = {(R)co, (R)(-s)};
+  }
+}
+
+}  // namespace dd

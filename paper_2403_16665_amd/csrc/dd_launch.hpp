@@ -1,0 +1,83 @@
+// dd_launch.hpp -- host-side launch entry points for the templated kernels.
+//
+// Each kernel is instantiated for a fixed set of line lengths; the host picks
+// the instantiation with a switch on the runtime length.  Launchers return
+// hipErrorInvalidValue for a length that is not instantiated.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dd_kernels.hpp"
+
+namespace dd {
+
+// Every line length a kernel is built for: 2^a (1..4096), 3*2^a (3..3072),
+// 5*2^a (5..2560).
+#define DD_ALL_LENGTHS(X)                                                                   \
+  X(1) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(3) \
+  X(6) X(12) X(24) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072) X(5) X(10) X(20)     \
+  X(40) X(80) X(160) X(320) X(640) X(1280) X(2560)
+
+// Lengths of the second pass (powers of two).
+#define DD_POW2_LENGTHS(X) \
+  X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+struct LaunchCfg {
+  int64_t grid;
+  int block;
+  size_t lds;
+  hipStream_t stream;
+};
+
+struct KGeom {
+  int TL;       // threads per line
+  int lines;    // default lines per block
+  int block;    // compile-time block size bound of the kernel
+};
+
+bool len_supported(int L);
+bool pass2_len_supported(int L);
+KGeom geom_single(int L, int rbytes);
+KGeom geom_pass(int L, int rbytes);
+
+// Overloads per arithmetic type R (float, double) and input type (real R or
+// complex cx<R>); defined in dd_single_*.hip / dd_pass_*.hip.
+#define DD_DECL_LAUNCHERS(R)                                                                     \
+  hipError_t launch_single(int L, const LaunchCfg& c, const R* x, cx<R>* X, const DenseArgs<R>& a);     \
+  hipError_t launch_single(int L, const LaunchCfg& c, const cx<R>* x, cx<R>* X, const DenseArgs<R>& a); \
+  hipError_t launch_pass1(int L, const LaunchCfg& c, const R* x, cx<R>* Y, const DenseArgs<R>& a);      \
+  hipError_t launch_pass1(int L, const LaunchCfg& c, const cx<R>* x, cx<R>* Y, const DenseArgs<R>& a);  \
+  hipError_t launch_pass2(int L, const LaunchCfg& c, const cx<R>* Y, cx<R>* X, const DenseArgs<R>& a);  \
+  hipError_t launch_twiddle(cx<R>* out, int64_t rows, int64_t cols, int64_t r0, int64_t den, int fp32, \
+                            hipStream_t s);
+DD_DECL_LAUNCHERS(float)
+DD_DECL_LAUNCHERS(double)
+#undef DD_DECL_LAUNCHERS
+
+// LDS bytes of each kernel for a given length and lines per block.
+inline size_t lds_single(int L, int lines, int alpha, int rbytes) {
+  return (size_t)lines * ((size_t)(L + L / 16 + 1) + (size_t)alpha * L) * 2 * rbytes;
+}
+inline size_t lds_pass1(int L, int lines, int rbytes) {
+  return (size_t)(L * lines + (L / 16 + 1) * 8) * 2 * rbytes;
+}
+inline size_t lds_pass2(int L, int lines, int rbytes) {
+  size_t a = (size_t)lines * (L + L / 16 + 1);
+  size_t b = (size_t)L * (lines + 1);
+  return (a > b ? a : b) * 2 * rbytes;
+}
+
+// Kernel launch with the dynamic-LDS attribute raised when needed.
+template <typename K, typename... Args>
+inline hipError_t launch_kernel(K kern, const LaunchCfg& c, Args... args) {
+  if (c.lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+    if (e != hipSuccess) return e;
+  }
+  if (c.grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kern, dim3((unsigned)c.grid), dim3(c.block), c.lds, c.stream, args...);
+  return hipGetLastError();
+}
+
+}  // namespace dd

@@ -1,0 +1,71 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/dense_dft.h declares, and rejects bad arguments before any device call."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dense_dft.h")
+LIB = os.path.join(ROOT, "paper_2403_16665_amd", "libdensedft.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dense_dft_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first"
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (dense_dft_\w+)", out))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    assert len(declared_functions()) >= 8
+
+
+def test_binding_loads_and_names_match():
+    import paper_2403_16665_amd as dd
+    for f in declared_functions():
+        assert hasattr(dd._lib, f)
+        assert hasattr(dd, f), f"binding lacks {f}"
+    assert dd.dense_dft_version() >= 100
+    assert dd.dense_dft_status_string(0) == "ok"
+    assert "unsupported" in dd.dense_dft_status_string(2)
+
+
+@pytest.mark.parametrize("N,alpha,T,batch,dtype,flags,want", [
+    (0, 2, 1.0, 1, 1, 0, 1),                 # N < 1
+    (64, 2, 0.0, 1, 1, 0, 1),                # T <= 0
+    (64, 2, float("inf"), 1, 1, 0, 1),       # T not finite
+    (64, 2, float("nan"), 1, 1, 0, 1),
+    (64, 2, 1.0, 0, 1, 0, 1),                # batch < 1
+    (64, 2, 1.0, 1, 7, 0, 1),                # bad dtype
+    (64, 2, 1.0, 1, 1, 8, 1),                # unknown flag
+    (64, 0, 1.0, 1, 1, 0, 2),                # alpha < 1 (alpha < 1 is a one-way transform; unsupported)
+    (64, -3, 1.0, 1, 1, 0, 2),
+    (7, 2, 1.0, 1, 1, 0, 2),                 # prime factor > 5
+    (1 << 20, 4096, 1.0, 1, 1, 0, 2),        # alpha*N > 2^31
+])
+def test_plan_rejects_bad_arguments(N, alpha, T, batch, dtype, flags, want):
+    import ctypes
+    import paper_2403_16665_amd as dd
+    h = ctypes.c_void_p(12345)
+    rc = dd._lib.dense_dft_plan(ctypes.byref(h), N, alpha, T, batch, dtype, flags)
+    assert rc == want
+    assert not h.value  # out-param cleared on failure
+
+
+def test_null_handles_rejected():
+    import ctypes
+    import paper_2403_16665_amd as dd
+    assert dd._lib.dense_dft_plan(None, 64, 2, 1.0, 1, 1, 0) == 1
+    assert dd._lib.dense_dft_exec(None, None, None, None, None) == 1
+    assert dd._lib.dense_dft_destroy(None) == 1
+    n = ctypes.c_size_t()
+    assert dd._lib.dense_dft_workspace_size(None, ctypes.byref(n)) == 1
+    assert dd._lib.dense_dft_plan_info(None, None, None, None) == 1
+    assert dd._lib.dense_dft_profile_begin(None, 4) == 1
