@@ -135,6 +135,79 @@ dd_status dense_dft_profile_begin(dd_plan_t plan, int32_t max_launches);
 dd_status dense_dft_profile_end(dd_plan_t plan, int32_t *kinds, float *ms,
                                 int32_t cap, int32_t *count);
 
+/* ---- Many signals of uneven N and alpha in one persistent launch ----
+ *
+ * One descriptor per signal (the problem of Section 2 for each: N samples
+ * over [0, T], dense factor alpha):
+ *   N, alpha, T : as for dense_dft_plan (integer alpha >= 1, T > 0);
+ *   dtype       : input dtype; output complex64 for DD_F32 / DD_C64,
+ *                 complex128 for DD_F64 / DD_C128;
+ *   x           : device, [N] input of `dtype`;
+ *   X           : device, [alpha*N] output, must not overlap any x.
+ */
+typedef struct dd_desc {
+    int64_t N;
+    int32_t alpha;
+    double T;
+    dd_dtype dtype;
+    const void *x;
+    void *X;
+} dd_desc;
+
+typedef struct dd_batch *dd_batch_t;
+
+/* Plan a batch: validate every descriptor, choose each signal's schedule
+ * (one pass, or two passes N = N1*N2, as dense_dft_plan does), generate the
+ * twiddle tables of every distinct (N, alpha) on the GPU in FP64 (rounded
+ * once; DD_TWIDDLE_FP32 as for plans), allocate the scratch of the two-pass
+ * signals, and build the device work list: one task per block-sized piece
+ * (a single-pass signal, a pass-1 column tile, a pass-2 row block), queued
+ * so that every task depends only on tasks queued before it.  FP32/complex64
+ * signals of the compiled lengths run in the persistent kernel; the others
+ * (FP64 dtypes, other lengths) run as plain per-signal executions after it.
+ * The descriptors are copied; the caller keeps ownership of x and X.
+ * Errors: DD_ERR_INVALID (count < 1, bad descriptor, null or misaligned
+ * pointer, T <= 0), DD_ERR_UNSUPPORTED (as dense_dft_plan), DD_ERR_NOMEM,
+ * DD_ERR_DEVICE. */
+dd_status dense_dft_batch_plan(dd_batch_t *out, const dd_desc *descs,
+                               int32_t count, uint32_t flags);
+
+/* Enqueue the whole batch on `stream`: an asynchronous copy of the
+ * descriptor table from pinned host memory, a reset of the two queue heads,
+ * two launches of the persistent queue kernel (a fixed grid sized to the
+ * device's occupancy; its blocks take tasks until the queue is empty): the
+ * first runs every single-pass and pass-1 task, the second every pass-2
+ * task, so no block waits for another; then the plain executions of the
+ * fallback signals.  Nothing synchronises, no
+ * memory is allocated and no memset is enqueued, so the call can be captured
+ * in a HIP graph; a replay re-reads the descriptor table at replay time.
+ * Executions of one batch must not overlap in time. */
+dd_status dense_dft_batch_exec(dd_batch_t b, void *stream);
+
+/* Point the batch at new buffers of the same shapes: descs[i] must match the
+ * planned descriptor i in N, alpha, T and dtype.  Takes effect at the next
+ * execution or graph replay; the caller must ensure no execution of the
+ * batch is in flight.  Errors: DD_ERR_INVALID (count or shape mismatch,
+ * bad pointer). */
+dd_status dense_dft_batch_set_buffers(dd_batch_t b, const dd_desc *descs,
+                                      int32_t count);
+
+/* Synchronise the batch's device; *flags is set to 0 (reserved).  Returns
+ * DD_ERR_DEVICE if the device reports an error. */
+dd_status dense_dft_batch_status(dd_batch_t b, uint32_t *flags);
+
+/* Sizes of the planned batch: tasks in the persistent queue, blocks of its
+ * launch, bytes of scratch, signals run as fallback executions. */
+dd_status dense_dft_batch_info(dd_batch_t b, int32_t *tasks, int32_t *grid,
+                               size_t *scratch_bytes, int32_t *fallback);
+
+/* Free the batch (synchronises its device). */
+dd_status dense_dft_batch_destroy(dd_batch_t b);
+
+/* Convenience: plan, execute on `stream`, synchronise it, and free. */
+dd_status dense_dft_exec_many(const dd_desc *descs, int32_t count,
+                              void *stream);
+
 /* Static text for a status code. */
 const char *dense_dft_status_string(dd_status status);
 

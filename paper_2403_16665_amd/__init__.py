@@ -49,6 +49,29 @@ _lib.dense_dft_profile_begin.restype = ctypes.c_int
 _lib.dense_dft_profile_end.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
 _lib.dense_dft_profile_end.restype = ctypes.c_int
+
+
+class dd_desc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("alpha", ctypes.c_int32), ("T", ctypes.c_double),
+                ("dtype", ctypes.c_int), ("x", ctypes.c_void_p), ("X", ctypes.c_void_p)]
+
+
+_lib.dense_dft_batch_plan.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(dd_desc), ctypes.c_int32,
+                                      ctypes.c_uint32]
+_lib.dense_dft_batch_plan.restype = ctypes.c_int
+_lib.dense_dft_batch_exec.argtypes = [_vp, _vp]
+_lib.dense_dft_batch_exec.restype = ctypes.c_int
+_lib.dense_dft_batch_set_buffers.argtypes = [_vp, ctypes.POINTER(dd_desc), ctypes.c_int32]
+_lib.dense_dft_batch_set_buffers.restype = ctypes.c_int
+_lib.dense_dft_batch_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32)]
+_lib.dense_dft_batch_status.restype = ctypes.c_int
+_lib.dense_dft_batch_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32)]
+_lib.dense_dft_batch_info.restype = ctypes.c_int
+_lib.dense_dft_batch_destroy.argtypes = [_vp]
+_lib.dense_dft_batch_destroy.restype = ctypes.c_int
+_lib.dense_dft_exec_many.argtypes = [ctypes.POINTER(dd_desc), ctypes.c_int32, _vp]
+_lib.dense_dft_exec_many.restype = ctypes.c_int
 _lib.dense_dft_status_string.argtypes = [ctypes.c_int]
 _lib.dense_dft_status_string.restype = ctypes.c_char_p
 _lib.dense_dft_version.argtypes = []
@@ -78,6 +101,8 @@ def dense_dft_version() -> int:
 class Plan:
     """Owning handle of a dd_plan_t; destroyed when garbage-collected."""
 
+    _destroy = _lib.dense_dft_destroy  # kept on the class: usable at interpreter exit
+
     def __init__(self, handle, N, alpha, T, batch, dtype, flags):
         self.handle = handle
         self.N, self.alpha, self.T, self.batch = N, alpha, T, batch
@@ -90,7 +115,7 @@ class Plan:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:
-            _lib.dense_dft_destroy(h)
+            Plan._destroy(h)
             self.handle = None
 
 
@@ -155,6 +180,85 @@ def dense_dft_destroy(plan: Plan) -> None:
     if plan.handle:
         _check(_lib.dense_dft_destroy(plan.handle), "dense_dft_destroy")
         plan.handle = None
+
+
+# --- many signals of uneven N and alpha in one persistent launch ---
+class Batch:
+    """Owning handle of a dd_batch_t."""
+
+    _destroy = _lib.dense_dft_batch_destroy
+
+    def __init__(self, handle, count):
+        self.handle = handle
+        self.count = count
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            Batch._destroy(h)
+            self.handle = None
+
+
+def _desc_array(descs):
+    """descs: iterable of (N, alpha, T, dtype, x_tensor, X_tensor) or dd_desc."""
+    items = list(descs)
+    arr = (dd_desc * len(items))()
+    for i, d in enumerate(items):
+        if isinstance(d, dd_desc):
+            arr[i] = d
+        else:
+            N, alpha, T, dtype, x, X = d
+            arr[i] = dd_desc(int(N), int(alpha), float(T), int(dtype),
+                             None if x is None else x.data_ptr(), None if X is None else X.data_ptr())
+    return arr, len(items)
+
+
+def dense_dft_batch_plan(descs, flags: int = DD_TWIDDLE_FP64) -> Batch:
+    arr, n = _desc_array(descs)
+    h = _vp()
+    _check(_lib.dense_dft_batch_plan(ctypes.byref(h), arr, n, int(flags)), "dense_dft_batch_plan")
+    return Batch(h, n)
+
+
+def dense_dft_batch_exec(batch: Batch, stream=None) -> None:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(_lib.dense_dft_batch_exec(batch.handle, _vp(stream)), "dense_dft_batch_exec")
+
+
+def dense_dft_batch_set_buffers(batch: Batch, descs) -> None:
+    arr, n = _desc_array(descs)
+    _check(_lib.dense_dft_batch_set_buffers(batch.handle, arr, n), "dense_dft_batch_set_buffers")
+
+
+def dense_dft_batch_status(batch: Batch) -> int:
+    f = ctypes.c_uint32()
+    _check(_lib.dense_dft_batch_status(batch.handle, ctypes.byref(f)), "dense_dft_batch_status")
+    return int(f.value)
+
+
+def dense_dft_batch_info(batch: Batch):
+    """(tasks, grid, scratch_bytes, fallback_signals)."""
+    t, g, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    sb = ctypes.c_size_t()
+    _check(_lib.dense_dft_batch_info(batch.handle, ctypes.byref(t), ctypes.byref(g), ctypes.byref(sb),
+                                     ctypes.byref(f)), "dense_dft_batch_info")
+    return int(t.value), int(g.value), int(sb.value), int(f.value)
+
+
+def dense_dft_batch_destroy(batch: Batch) -> None:
+    if batch.handle:
+        _check(_lib.dense_dft_batch_destroy(batch.handle), "dense_dft_batch_destroy")
+        batch.handle = None
+
+
+def dense_dft_exec_many(descs, stream=None) -> None:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    arr, n = _desc_array(descs)
+    _check(_lib.dense_dft_exec_many(arr, n, _vp(stream)), "dense_dft_exec_many")
 
 
 # --- torch conveniences (memory allocation only) ---

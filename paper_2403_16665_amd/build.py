@@ -22,9 +22,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
 
 
 def sources():
-    out = [f for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")]
-    out.append("dd_api.cpp")
-    return out
+    return [f for f in sorted(os.listdir(CSRC)) if f.endswith((".hip", ".cpp"))]
 
 
 def build(jobs: int | None = None, verbose: bool = False) -> str:

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/dense_dft.h"
+#include "dd_host.hpp"
 #include "dd_launch.hpp"
 
 using namespace dd;
@@ -31,7 +32,7 @@ struct dd_plan {
   int s_lines = 1, s_TL = 1;
   size_t s_lds = 0;
   // two passes
-  int p1_lines = 1, p1_TL = 1, p1_ntile = 1, p1_jgroup = 1, p1_njg = 1;
+  int p1_lines = 1, p1_TL = 1, p1_ntile = 1, p1_jgroup = 1, p1_njg = 1, p1_pre_lds = 0;
   size_t p1_lds = 0;
   int p2_lines = 1, p2_TL = 1, p2_ntile = 1;
   size_t p2_lds = 0;
@@ -53,27 +54,7 @@ struct dd_plan {
 
 namespace {
 
-bool is_smooth(int64_t n) {
-  if (n < 1) return false;
-  while (n % 2 == 0) n /= 2;
-  while (n % 3 == 0) n /= 3;
-  while (n % 5 == 0) n /= 5;
-  return n == 1;
-}
-
-int ilog2(int64_t v) {
-  int r = 0;
-  while ((int64_t)1 << (r + 1) <= v) ++r;
-  return r;
-}
-
 size_t cx_bytes(const dd_plan* p) { return (size_t)2 * p->rbytes; }
-
-dd_status hip_status(hipError_t e) {
-  if (e == hipSuccess) return DD_OK;
-  if (e == hipErrorOutOfMemory) return DD_ERR_NOMEM;
-  return DD_ERR_DEVICE;
-}
 
 void free_events(dd_plan* p) {
   for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
@@ -109,36 +90,13 @@ void free_tables(dd_plan* p) {
   }
 }
 
-// Stage twiddle table of a line plan: for each stage st >= 1 the block
-// [s][k] = W_{NS RAD}^{k s} (s < RAD, k < NS).
 dd_status gen_stage_table(dd_plan* p, void** out, int L, bool fp32, hipStream_t s) {
-  LinePlan lp = make_line_plan(L);
-  const int n = line_tw_size(lp);
-  const size_t bytes = (size_t)(n > 0 ? n : 1) * cx_bytes(p);
-  hipError_t e = hipMalloc(out, bytes);
-  if (e != hipSuccess) return hip_status(e);
-  for (int st = 1; st < lp.nst; ++st) {
-    const int NS = line_ns(lp, st), RAD = lp.rad[st];
-    const int off = line_tw_offset(lp, st);
-    if (p->dbl)
-      e = launch_twiddle(static_cast<cx<double>*>(*out) + off, RAD, NS, 0, (int64_t)NS * RAD, 0, s);
-    else
-      e = launch_twiddle(static_cast<cx<float>*>(*out) + off, RAD, NS, 0, (int64_t)NS * RAD, fp32, s);
-    if (e != hipSuccess) return hip_status(e);
-  }
-  return DD_OK;
+  return make_stage_table(out, L, p->dbl, fp32, s);
 }
 
-// out[r][c] = W_den^{(r c) mod den}
 dd_status gen_table(dd_plan* p, void** out, int64_t rows, int64_t cols, int64_t den, bool fp32,
                     hipStream_t s) {
-  hipError_t e = hipMalloc(out, (size_t)(rows * cols) * cx_bytes(p));
-  if (e != hipSuccess) return hip_status(e);
-  if (p->dbl)
-    e = launch_twiddle(static_cast<cx<double>*>(*out), rows, cols, 0, den, 0, s);
-  else
-    e = launch_twiddle(static_cast<cx<float>*>(*out), rows, cols, 0, den, fp32, s);
-  return hip_status(e);
+  return make_table(out, rows, cols, den, p->dbl, fp32, s);
 }
 
 // Choose N = N1 * N2 for the two-pass schedule: N1 any instantiated length,
@@ -248,7 +206,6 @@ dd_status dense_dft_plan(dd_plan_t* out, int64_t N, int32_t alpha, double T, int
     p->p1_lines = g1.lines;  // compile-time column count of the kernel
     p->p1_TL = g1.TL;
     p->p1_ntile = (int)((N2 + g1.lines - 1) / g1.lines);
-    p->p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes);
     p->p2_lines = g2.lines;
     p->p2_TL = g2.TL;
     p->p2_ntile = (int)((alpha * N1 + g2.lines - 1) / g2.lines);
@@ -273,6 +230,10 @@ dd_status dense_dft_plan(dd_plan_t* out, int64_t N, int32_t alpha, double T, int
     }
     p->p1_jgroup = jg;
     p->p1_njg = (alpha + jg - 1) / jg;
+    // stage the block's pre-twiddles in LDS when they take at most 16 KiB
+    const size_t pre_bytes = (size_t)jg * N1 * cx_bytes(p);
+    p->p1_pre_lds = pre_bytes <= 16 * 1024 ? 1 : 0;
+    p->p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, p->p1_pre_lds ? jg * (int)N1 : 0);
     p->ws_bytes = (size_t)chunk * per_sig;
   }
 
@@ -347,6 +308,7 @@ dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s
     a1.ntile = p->p1_ntile;
     a1.jgroup = p->p1_jgroup;
     a1.njg = p->p1_njg;
+    a1.pre_lds = p->p1_pre_lds;
     a1.scale = scale;
     a1.twL = static_cast<const cx<R>*>(p->twL1);
     a1.twPre = static_cast<const cx<R>*>(p->twPre);

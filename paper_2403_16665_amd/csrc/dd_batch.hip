@@ -1,0 +1,139 @@
+// dd_batch.hip -- the persistent batch kernel and its launchers.
+#include "dd_batch.hpp"
+#include "dd_launch.hpp"
+
+namespace dd {
+
+__global__ void k_batch_reset(unsigned* __restrict__ ctl) {
+  if (threadIdx.x < 2) ctl[threadIdx.x] = 0u;
+}
+
+// One task of each code path.
+__device__ __forceinline__ DenseArgs<float> item_args(const BatchItem& it) {
+  DenseArgs<float> a{};
+  a.batch = 1;
+  a.x_stride = it.N;
+  a.y_stride = (int64_t)it.alpha * it.N;
+  a.N1 = it.N1;
+  a.N2 = it.N2;
+  a.alpha = it.alpha;
+  a.jgroup = it.jgroup;
+  a.njg = it.njg;
+  a.pre_lds = it.pre_lds;
+  a.scale = it.scale;
+  a.twPre = it.twPre;
+  a.twQ = it.twQ;
+  a.twPost = it.twPost;
+  return a;
+}
+
+template <int L>
+__device__ __forceinline__ void run_single(const BatchItem* __restrict__ items, int item, int sub, unsigned char* smem,
+                                           int tid) {
+  const BatchItem& it = items[item];
+  DenseArgs<float> a = item_args(it);
+  a.lines = it.lines1;
+  a.twL = it.twL1;
+  body_single<float, AnyIn<float>, L>(AnyIn<float>{it.x, it.real}, it.X, a, sub, BATCH_THREADS, smem, tid);
+}
+
+template <int L>
+__device__ __forceinline__ void run_pass1(const BatchItem* __restrict__ items, int item, int sub, unsigned char* smem,
+                                          int tid) {
+  const BatchItem& it = items[item];
+  DenseArgs<float> a = item_args(it);
+  a.lines = batch_lines(L);
+  a.ntile = it.ntile1;
+  a.twL = it.twL1;
+  body_pass1<float, AnyIn<float>, L, batch_lines(L)>(AnyIn<float>{it.x, it.real}, it.Y, a, sub, smem, tid);
+}
+
+template <int L>
+__device__ __forceinline__ void run_pass2(const BatchItem* __restrict__ items, int item, int sub, unsigned char* smem,
+                                          int tid) {
+  const BatchItem& it = items[item];
+  DenseArgs<float> a = item_args(it);
+  a.lines = batch_lines(L);
+  a.ntile = it.ntile2;
+  a.twL = it.twL2;
+  body_pass2<float, L, batch_lines(L)>(it.Y, it.X, a, sub, smem, tid);
+}
+
+// Persistent queue over tasks [first, first + count): every block takes the
+// next task until the queue is empty.  No task of a launch depends on another
+// task of the same launch (pass-2 tasks run in a second launch), so no block
+// ever waits for another.
+__global__ __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_batch(
+    const BatchItem* __restrict__ items, const BatchTask* __restrict__ tasks, int first, int count,
+    unsigned* __restrict__ head) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_task;
+  for (;;) {
+    if (threadIdx.x == 0) s_task = (int)atomicAdd(head, 1u);
+    __syncthreads();
+    // uniform task index: the switch below is a scalar branch, not a
+    // divergent one (which would merge the live ranges of every code path)
+    const int ti = __builtin_amdgcn_readfirstlane(s_task);
+    __syncthreads();  // every thread has read s_task before thread 0 overwrites it
+    if (ti >= count) break;
+    const BatchTask tk = tasks[first + ti];
+    // The thread index passes through an opaque move every iteration, so that
+    // no code path's thread-dependent address arithmetic is hoisted out of
+    // the task loop (hoisted, the invariants of all paths stay live at once).
+    int tid;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+    switch (tk.w) {
+#define DD_S(LL)                                   \
+  case batch_code(BK_SINGLE, LL):                  \
+    run_single<LL>(items, tk.x, tk.z, smem, tid);  \
+    break;
+      DD_BATCH_SINGLE(DD_S)
+#undef DD_S
+#define DD_P1(LL)                                  \
+  case batch_code(BK_PASS1, LL):                   \
+    run_pass1<LL>(items, tk.x, tk.z, smem, tid);   \
+    break;
+      DD_BATCH_P1(DD_P1)
+#undef DD_P1
+#define DD_P2(LL)                                  \
+  case batch_code(BK_PASS2, LL):                   \
+    run_pass2<LL>(items, tk.x, tk.z, smem, tid);   \
+    break;
+      DD_BATCH_P2(DD_P2)
+#undef DD_P2
+      default:
+        break;
+    }
+  }
+}
+
+hipError_t launch_batch(const BatchItem* items, const BatchTask* tasks, int n_first, int n_second, unsigned* ctl,
+                        int grid1, int grid2, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (lds > 64 * 1024) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (n_first > 0) {
+    hipLaunchKernelGGL(k_batch, dim3(grid1), dim3(BATCH_THREADS), lds, s, items, tasks, 0, n_first, ctl);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (n_second > 0) {
+    hipLaunchKernelGGL(k_batch, dim3(grid2), dim3(BATCH_THREADS), lds, s, items, tasks, n_first, n_second,
+                       ctl + 1);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+int batch_max_blocks_per_cu(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch, BATCH_THREADS, lds) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
+
+}  // namespace dd

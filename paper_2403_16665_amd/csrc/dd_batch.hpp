@@ -1,0 +1,75 @@
+// dd_batch.hpp -- persistent batched execution of many alpha-dense DFTs of
+// uneven N and alpha in one launch (definitions shared by host and device).
+//
+// Every signal of a batch is an "item" with its own schedule (one pass, or
+// two passes N = N1 N2) and twiddle tables.  Its work is cut into block-sized
+// tasks: single-pass signals, pass-1 column tiles and pass-2 row blocks.  A
+// launch of k_batch runs a fixed grid of 256-thread blocks that take tasks
+// from a device queue until it is empty.  The single-pass and pass-1 tasks of
+// all items form the first launch, the pass-2 tasks the second, so the kernel
+// boundary publishes every scratch row before it is read and no block ever
+// waits for another.
+#pragma once
+
+#include "dd_kernels.hpp"
+
+namespace dd {
+
+constexpr int BATCH_THREADS = 256;
+constexpr int BATCH_LDS_MAX = 64 * 1024;
+
+// Lengths compiled into the batch kernel, per kind.
+#define DD_BATCH_SINGLE(X) \
+  X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(384) X(768) X(1536) X(3072) X(320) X(640) X(1280) X(2560)
+#define DD_BATCH_P1(X) X(32) X(64) X(128) X(256) X(512) X(48) X(96) X(192) X(384) X(40) X(80) X(160) X(320)
+#define DD_BATCH_P2(X) X(32) X(64) X(128) X(256) X(512)
+
+enum BatchKind { BK_SINGLE = 0, BK_PASS1 = 1, BK_PASS2 = 2 };
+
+// code = kind * 64 + L's position in the kind's list; -1 if not compiled.
+__host__ __device__ constexpr int batch_code(int kind, int L) {
+  int i = 0;
+#define DD_POS(LL) \
+  if (LL == L) return kind * 64 + i; \
+  ++i;
+  if (kind == BK_SINGLE) {
+    DD_BATCH_SINGLE(DD_POS)
+  } else if (kind == BK_PASS1) {
+    DD_BATCH_P1(DD_POS)
+  } else if (kind == BK_PASS2) {
+    DD_BATCH_P2(DD_POS)
+  }
+#undef DD_POS
+  return -1;
+}
+
+// Lines per 256-thread block for a pass kernel of length L.
+__host__ __device__ constexpr int batch_lines(int L) { return BATCH_THREADS / line_threads(L); }
+
+// Device descriptor of one signal of a batch (FP32 arithmetic; real float or
+// complex float input).
+struct BatchItem {
+  const void* x;          // [N] input
+  cx<float>* X;           // [alpha N] output
+  cx<float>* Y;           // [alpha N] scratch (two-pass items)
+  const cx<float>* twL1;  // stage twiddles of the N1 line (N for one pass)
+  const cx<float>* twPre; // [j][n1] W_{alpha N1}^{j n1}
+  const cx<float>* twQ;   // [j][n2] W_{alpha N}^{j n2}
+  const cx<float>* twPost;// [k1][n2] W_N^{k1 n2}
+  const cx<float>* twL2;  // stage twiddles of the N2 line
+  int64_t N;
+  int N1, N2, alpha, real;
+  int lines1, ntile1, jgroup, njg, pre_lds;  // one pass: lines1 = signals per block (1)
+  int ntile2;
+  int p1_tasks;           // pass-1 tasks of the item
+  int code1, code2;       // code paths: single or pass 1; pass 2
+  float scale;            // T / N
+  int pad_;
+};
+
+// Task: x = item, y = kind, z = block index within the item's pass, w = code.
+using BatchTask = int4;
+
+// Control words: [0] queue head of the first launch, [1] of the second.
+
+}  // namespace dd

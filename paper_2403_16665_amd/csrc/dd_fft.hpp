@@ -254,14 +254,28 @@ struct ColLayout {
   static __host__ __device__ constexpr int elems(int L) { return L * LINES + (L / 16 + 1) * 8; }
 };
 
+// Exchange synchronisation between radix stages: the whole block, or only the
+// wavefront when every line lies inside one wavefront (LDS operations of a
+// wavefront complete in order; the fence keeps the compiler from moving LDS
+// accesses across it).
+template <bool WAVE>
+__device__ __forceinline__ void exchange_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham stage.  On entry (first stage) v[e] holds line element t + TL e.
 // Butterfly b = t + TL i (i < NB = EPT/RAD) reads elements b + s L/RAD,
 // twiddles them by W_{NS RAD}^{(b mod NS) s}, applies the RAD-point DFT and
 // writes output s to position (b / NS) NS RAD + b mod NS + s NS.  After the
 // last stage v[e] holds output element k = t + TL e (natural order).
-template <typename R, int L, int ST, class Lay>
+template <typename R, int L, int ST, bool WAVE, class Lay>
 __device__ __forceinline__ void line_stage(cx<R>* v, int t, cx<R>* lds, const Lay& lay,
-                                           const cx<R>* __restrict__ twL) {
+                                           const cx<R>* __restrict__ twL, bool act) {
   constexpr LinePlan P = make_line_plan(L);
   constexpr int EPT = P.EPT;
   constexpr int TL = L / EPT;
@@ -275,7 +289,7 @@ __device__ __forceinline__ void line_stage(cx<R>* v, int t, cx<R>* lds, const La
     for (int i = 0; i < NB; ++i) {
       const int b = t + TL * i;
 #pragma unroll
-      for (int s = 0; s < RAD; ++s) v[i + s * NB] = lds[lay(b + s * (L / RAD))];
+      for (int s = 0; s < RAD; ++s) v[i + s * NB] = act ? lds[lay(b + s * (L / RAD))] : v[i + s * NB];
     }
     const cx<R>* __restrict__ tws = twL + line_tw_offset(P, ST);
 #pragma unroll
@@ -289,27 +303,31 @@ __device__ __forceinline__ void line_stage(cx<R>* v, int t, cx<R>* lds, const La
 #pragma unroll
   for (int i = 0; i < NB; ++i) dft<R, RAD, NB>(v + i);
   if constexpr (!LAST) {
-    __syncthreads();  // every thread has read its inputs of this stage
+    exchange_sync<WAVE>();  // every thread has read its inputs of this stage
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int b = t + TL * i;
       const int base = (b / NS) * NS * RAD + (b % NS);
 #pragma unroll
-      for (int s = 0; s < RAD; ++s) lds[lay(base + s * NS)] = v[i + s * NB];
+      for (int s = 0; s < RAD; ++s)
+        if (act) lds[lay(base + s * NS)] = v[i + s * NB];
     }
-    __syncthreads();
-    line_stage<R, L, ST + 1, Lay>(v, t, lds, lay, twL);
+    exchange_sync<WAVE>();
+    line_stage<R, L, ST + 1, WAVE, Lay>(v, t, lds, lay, twL, act);
   }
 }
 
-// Forward length-L transform of one line.  All threads of the block must call
-// it (it contains barriers; the first one also orders it after any earlier
-// use of `lds`).  twL is the stage twiddle table (line_tw_size entries).
-template <typename R, int L, class Lay>
+// Forward length-L transform of one line.  All threads of the block (WAVE
+// false) or of the wavefront (WAVE true, every line inside one wavefront)
+// must call it; its first synchronisation also orders it after any earlier
+// use of `lds`.  twL is the stage twiddle table (line_tw_size entries).
+// Threads with act == false take part in the synchronisation only (no LDS
+// access); their registers come out unchanged.
+template <typename R, int L, bool WAVE, class Lay>
 __device__ __forceinline__ void line_fft(cx<R>* v, int t, cx<R>* lds, const Lay& lay,
-                                         const cx<R>* __restrict__ twL) {
+                                         const cx<R>* __restrict__ twL, bool act = true) {
   constexpr LinePlan P = make_line_plan(L);
-  if constexpr (P.nst > 0) line_stage<R, L, 0, Lay>(v, t, lds, lay, twL);
+  if constexpr (P.nst > 0) line_stage<R, L, 0, WAVE, Lay>(v, t, lds, lay, twL, act);
 }
 
 }  // namespace dd

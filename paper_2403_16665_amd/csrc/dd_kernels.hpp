@@ -35,6 +35,7 @@ struct DenseArgs {
   int lines;          // lines per block: signals (single), columns (pass 1), rows (pass 2)
   int ntile;          // column tiles (pass 1) or row blocks (pass 2) per signal
   int jgroup, njg;    // j values per block and number of j groups (pass 1)
+  int pre_lds;        // pass 1: pre-twiddles of the block's j range staged in LDS
   R scale;            // T / N
   const cx<R>* twL;   // stage twiddles of the line FFT of this kernel ([s][k] per stage)
   const cx<R>* twPre; // W_{alpha N1}^{j n1}, laid out [j][n1]
@@ -46,6 +47,25 @@ template <typename R> __device__ __forceinline__ cx<R> load_in(const float* p, i
 template <typename R> __device__ __forceinline__ cx<R> load_in(const double* p, int64_t i) { return {(R)p[i], (R)0}; }
 template <typename R> __device__ __forceinline__ cx<R> load_in(const cx<float>* p, int64_t i) { cx<float> v = p[i]; return {(R)v.re, (R)v.im}; }
 template <typename R> __device__ __forceinline__ cx<R> load_in(const cx<double>* p, int64_t i) { cx<double> v = p[i]; return {(R)v.re, (R)v.im}; }
+
+// Input accessors: element (base + off) of a signal's samples as cx<R>.  The
+// base is uniform across the block, the offset per lane (keeps the address
+// arithmetic in scalar registers).
+template <typename R, typename In>
+struct PtrIn {
+  const In* p;
+  __device__ __forceinline__ cx<R> operator()(int64_t base, unsigned off) const { return load_in<R>(p + base, off); }
+};
+// Runtime choice between real float and complex float samples (mixed batches).
+template <typename R>
+struct AnyIn {
+  const void* p;
+  int real;
+  __device__ __forceinline__ cx<R> operator()(int64_t base, unsigned off) const {
+    return real ? load_in<R>(static_cast<const float*>(p) + base, off)
+                : load_in<R>(static_cast<const cx<float>*>(p) + base, off);
+  }
+};
 
 // Launch geometry shared by host and device: lines per block so that the
 // block has at most `max_threads` threads and its line data fits `lds_budget`.
@@ -74,36 +94,41 @@ struct Geom {
   static constexpr int BLOCK_SINGLE = TL * lines_single();
 };
 
+// LDS elements of pass 1 for a tile of C columns (host and device): the
+// exchange buffer, the stage twiddles and `pre` staged pre-twiddles.
+__host__ __device__ constexpr int pass1_lds_elems(int L, int C, int pre) {
+  return L * C + (L / 16 + 1) * 8 + line_tw_size(make_line_plan(L)) + pre;
+}
+
 // ---------------------------------------------------------------------------
-// Single pass: block = `lines` signals; thread t of line `line` owns samples
-// t + TL e.  Dynamic LDS: exchange (RowLayout) then the spectrum image.
+// Block bodies.  `bid` is the block's index in its launch (or the task index
+// of a persistent batch), `nt` the number of threads taking part, `smem` the
+// dynamic LDS base, `tid` the thread's index in the block.
 // ---------------------------------------------------------------------------
-template <typename R, typename In, int L, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_single(const In* __restrict__ x, cx<R>* __restrict__ X,
-                                                  DenseArgs<R> a) {
+
+// Single pass: block = a.lines signals; thread t of line `line` owns samples
+// t + TL e.  LDS: exchange (RowLayout, a.lines lines) then the spectrum image.
+// Threads beyond a.lines * TL only take part in synchronisation.
+template <typename R, class InAcc, int L>
+__device__ __forceinline__ void body_single(const InAcc& x, cx<R>* __restrict__ X, const DenseArgs<R>& a,
+                                            int64_t bid, int nt, unsigned char* smem, int tid) {
   constexpr LinePlan P = make_line_plan(L);
   constexpr int EPT = P.EPT;
   constexpr int TL = L / EPT;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<R>* ex = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* ex = reinterpret_cast<cx<R>*>(smem);
   cx<R>* img = ex + RowLayout<L>::elems(a.lines);
-  const int tid = threadIdx.x;
   const int t = tid % TL, line = tid / TL;
-  const int64_t sig0 = (int64_t)blockIdx.x * a.lines;
+  const bool act = line < a.lines;
+  const int64_t sig0 = bid * a.lines;
   const int64_t sig = sig0 + line;
-  const bool active = sig < a.batch;
+  const bool active = act && sig < a.batch;
   const int M1 = a.alpha * L;
 
   cx<R> xv[EPT];
-  if (active) {
-    const In* xs = x + sig * a.x_stride;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) xv[e] = cscale(load_in<R>(xs, t + TL * e), a.scale);
-  } else {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) xv[e] = {(R)0, (R)0};
-  }
-  const RowLayout<L> lay(line);
+  for (int e = 0; e < EPT; ++e)
+    xv[e] = active ? cscale(x(sig * a.x_stride, (unsigned)(t + TL * e)), a.scale) : cx<R>{(R)0, (R)0};
+  const RowLayout<L> lay(act ? line : 0);
   cx<R>* im = img + (int64_t)line * M1;
   for (int j = 0; j < a.alpha; ++j) {
     cx<R> v[EPT];
@@ -115,41 +140,60 @@ __global__ __launch_bounds__(BLOCK) void k_single(const In* __restrict__ x, cx<R
 #pragma unroll
       for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pre[TL * e]);
     }
-    line_fft<R, L>(v, t, ex, lay, a.twL);
+    line_fft<R, L, (TL <= 64)>(v, t, ex, lay, a.twL, act);
+    if (act) {
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) im[a.alpha * (t + TL * e) + j] = v[e];
+      for (int e = 0; e < EPT; ++e) im[a.alpha * (t + TL * e) + j] = v[e];
+    }
   }
   __syncthreads();
   const int64_t nl = min((int64_t)a.lines, a.batch - sig0);
   const int64_t total = nl * M1;
   cx<R>* dst = X + sig0 * a.y_stride;  // y_stride == alpha * L
-  for (int64_t i = tid; i < total; i += blockDim.x) dst[i] = img[i];
+  for (int64_t i = tid; i < total; i += nt) dst[i] = img[i];
+  __syncthreads();  // the image is reused by the next task of a persistent block
 }
 
-// ---------------------------------------------------------------------------
 // Pass 1: block = (signal, tile of C columns n2, group of j values).  Thread
 // (c, t) with c fastest owns column n2 = tile*C + c, samples n1 = t + TL e.
-// ---------------------------------------------------------------------------
-template <typename R, typename In, int L, int C>
-__global__ __launch_bounds__(C * (L / make_line_plan(L).EPT)) void k_pass1(const In* __restrict__ x, cx<R>* __restrict__ Y,
-                                                 DenseArgs<R> a) {
+// Output Y[alpha k1 + j][n2] times the inter-pass twiddle
+// W_{alpha N}^{m1 n2} = W_N^{k1 n2} W_{alpha N}^{j n2}.  (Applying it in pass 2
+// instead was measured slower: pass 2 is the more loaded of the two.)
+// Columns are fastest across the block so that every store instruction
+// writes whole 128-byte lines of C columns.  (A wavefront-private column
+// group would avoid the block barriers of the exchange but stores 32-byte
+// pieces that reach memory as partial lines: measured 1.8x the write
+// traffic.)
+template <typename R, class InAcc, int L, int C>
+__device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y, const DenseArgs<R>& a,
+                                           int64_t bid, unsigned char* smem, int tid) {
   constexpr LinePlan P = make_line_plan(L);
   constexpr int EPT = P.EPT;
   constexpr int TL = L / EPT;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<R>* ex = reinterpret_cast<cx<R>*>(smem_raw);
-  int64_t bid = blockIdx.x;
+  constexpr int NT = C * TL;
+  constexpr int TWN = line_tw_size(P);
+  cx<R>* ex = reinterpret_cast<cx<R>*>(smem);
+  cx<R>* tws = ex + ColLayout<C>::elems(L);   // stage twiddles
+  cx<R>* pre = tws + TWN;                     // [j - j0][n1] pre-twiddles (when a.pre_lds)
   const int jg = (int)(bid % a.njg);
   bid /= a.njg;
   const int tile = (int)(bid % a.ntile);
   const int64_t sig = bid / a.ntile;
-  const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
   const int N2 = a.N2;
   const int n2 = tile * C + c;
   const ColLayout<C> lay(c);
+  const int j0 = jg * a.jgroup;
+  const int j1 = min(a.alpha, j0 + a.jgroup);
 
-  const In* xs = x + sig * a.x_stride;
+  // twiddle tables of this block into LDS (read every j; from L2 their latency
+  // sits on the critical path of each iteration)
+  for (int i = tid; i < TWN; i += NT) tws[i] = a.twL[i];
+  if (a.pre_lds) {
+    const int n = (j1 - j0) * L;
+    for (int i = tid; i < n; i += NT) pre[i] = a.twPre[j0 * L + i];
+  }
+
   const bool colok = n2 < N2;  // a tile wider than N2 has idle columns
   cx<R> xv[EPT], pw[EPT];
   const unsigned in_off = (unsigned)(N2 * t + n2);          // lane part of N2 n1 + n2
@@ -157,29 +201,32 @@ __global__ __launch_bounds__(C * (L / make_line_plan(L).EPT)) void k_pass1(const
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     if (colok) {
-      xv[e] = cscale(load_in<R>(xs + in_step * e, in_off), a.scale);
+      xv[e] = cscale(x(sig * a.x_stride + (int64_t)in_step * e, in_off), a.scale);
       pw[e] = (a.twPost + in_step * e)[in_off];             // W_N^{k1 n2}, k1 = t + TL e
     } else {
       xv[e] = {(R)0, (R)0};
       pw[e] = {(R)0, (R)0};
     }
   }
+  __syncthreads();
   const unsigned out_off = (unsigned)(a.alpha * N2 * t + n2);  // lane part of (alpha k1 + j) N2 + n2
   const unsigned out_step = (unsigned)(a.alpha * N2 * TL);
   cx<R>* ys = Y + sig * a.y_stride;
-  const int j0 = jg * a.jgroup;
-  const int j1 = min(a.alpha, j0 + a.jgroup);
   for (int j = j0; j < j1; ++j) {
     cx<R> v[EPT];
     if (j == 0) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) v[e] = xv[e];
-    } else {
-      const cx<R>* __restrict__ pre = a.twPre + j * L + t;   // W_{alpha N1}^{j n1}
+    } else if (a.pre_lds) {
+      const cx<R>* pj = pre + (j - j0) * L + t;               // W_{alpha N1}^{j n1}
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pre[TL * e]);
+      for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pj[TL * e]);
+    } else {
+      const cx<R>* __restrict__ pj = a.twPre + j * L + t;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pj[TL * e]);
     }
-    line_fft<R, L>(v, t, ex, lay, a.twL);
+    line_fft<R, L, false>(v, t, ex, lay, tws);
     if (colok) {
       const cx<R> q = a.twQ[j * N2 + n2];  // W_{alpha N}^{j n2}
       cx<R>* yj = ys + (int64_t)j * N2;
@@ -187,25 +234,21 @@ __global__ __launch_bounds__(C * (L / make_line_plan(L).EPT)) void k_pass1(const
       for (int e = 0; e < EPT; ++e) (yj + out_step * e)[out_off] = cmul(v[e], cmul(pw[e], q));
     }
   }
+  __syncthreads();  // LDS tables are rewritten by the next task of a persistent block
 }
 
-// ---------------------------------------------------------------------------
-// Pass 2: block = (signal, block of R consecutive rows m1).  Thread (t, r)
-// with t fastest owns row m1 = block*R + r, elements n2 = t + TL e.  Output
-// X[m1 + alpha N1 k2] is staged in LDS and written as runs of R bins.
-// ---------------------------------------------------------------------------
+// Pass 2: block = (signal, block of RB consecutive rows m1).  Thread (t, r)
+// with t fastest owns row m1 = block*RB + r, elements n2 = t + TL e.  Output
+// X[m1 + alpha N1 k2] is staged in LDS and written as runs of RB bins.
 template <typename R, int L, int RB>
-__global__ __launch_bounds__(RB * (L / make_line_plan(L).EPT)) void k_pass2(const cx<R>* __restrict__ Y, cx<R>* __restrict__ X,
-                                                 DenseArgs<R> a) {
+__device__ __forceinline__ void body_pass2(const cx<R>* __restrict__ Y, cx<R>* __restrict__ X,
+                                           const DenseArgs<R>& a, int64_t bid, unsigned char* smem, int tid) {
   constexpr LinePlan P = make_line_plan(L);
   constexpr int EPT = P.EPT;
   constexpr int TL = L / EPT;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<R>* ex = reinterpret_cast<cx<R>*>(smem_raw);
-  const int64_t bid = blockIdx.x;
+  cx<R>* ex = reinterpret_cast<cx<R>*>(smem);
   const int rb = (int)(bid % a.ntile);
   const int64_t sig = bid / a.ntile;
-  const int tid = threadIdx.x;
   const int t = tid % TL, r = tid / TL;
   const int rows = a.alpha * a.N1;
   const int m1 = rb * RB + r;
@@ -216,7 +259,7 @@ __global__ __launch_bounds__(RB * (L / make_line_plan(L).EPT)) void k_pass2(cons
 #pragma unroll
   for (int e = 0; e < EPT; ++e) v[e] = ok ? (ys + TL * e)[row_off] : cx<R>{(R)0, (R)0};
   const RowLayout<L> lay(r);
-  line_fft<R, L>(v, t, ex, lay, a.twL);
+  line_fft<R, L, (TL <= 64)>(v, t, ex, lay, a.twL);
   __syncthreads();
   constexpr int SR = RB + 1;  // staging row stride (odd, spreads banks)
 #pragma unroll
@@ -231,6 +274,33 @@ __global__ __launch_bounds__(RB * (L / make_line_plan(L).EPT)) void k_pass2(cons
     const int m = rb * RB + rr;
     if (m < rows) xs[(int64_t)m + (int64_t)rows * k2] = ex[k2 * SR + rr];
   }
+  __syncthreads();  // the staging buffer is reused by the next task of a persistent block
+}
+
+// ---------------------------------------------------------------------------
+// Standalone kernels (one launch per pass).
+// ---------------------------------------------------------------------------
+template <typename R, typename In, int L, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_single(const In* __restrict__ x, cx<R>* __restrict__ X,
+                                                  DenseArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  body_single<R, PtrIn<R, In>, L>(PtrIn<R, In>{x}, X, a, blockIdx.x, blockDim.x, smem_raw, threadIdx.x);
+}
+
+template <typename R, typename In, int L, int C>
+__global__ __launch_bounds__(C * (L / make_line_plan(L).EPT)) void k_pass1(const In* __restrict__ x,
+                                                                          cx<R>* __restrict__ Y,
+                                                                          DenseArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  body_pass1<R, PtrIn<R, In>, L, C>(PtrIn<R, In>{x}, Y, a, blockIdx.x, smem_raw, threadIdx.x);
+}
+
+template <typename R, int L, int RB>
+__global__ __launch_bounds__(RB * (L / make_line_plan(L).EPT)) void k_pass2(const cx<R>* __restrict__ Y,
+                                                                           cx<R>* __restrict__ X,
+                                                                           DenseArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  body_pass2<R, L, RB>(Y, X, a, blockIdx.x, smem_raw, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

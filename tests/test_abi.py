@@ -69,3 +69,27 @@ def test_null_handles_rejected():
     assert dd._lib.dense_dft_workspace_size(None, ctypes.byref(n)) == 1
     assert dd._lib.dense_dft_plan_info(None, None, None, None) == 1
     assert dd._lib.dense_dft_profile_begin(None, 4) == 1
+
+
+def test_batch_plan_rejects_bad_descriptors():
+    import ctypes
+    import paper_2403_16665_amd as dd
+    h = ctypes.c_void_p(7)
+    ok = dd.dd_desc(1024, 4, 1.0, dd.DD_C64, 4096, 1 << 20)
+    arr = (dd.dd_desc * 1)(ok)
+    assert dd._lib.dense_dft_batch_plan(ctypes.byref(h), arr, 0, 0) == 1          # count < 1
+    assert not h.value
+    assert dd._lib.dense_dft_batch_plan(None, arr, 1, 0) == 1                     # null out
+    assert dd._lib.dense_dft_batch_plan(ctypes.byref(h), None, 1, 0) == 1        # null descs
+    for bad in [dd.dd_desc(0, 4, 1.0, dd.DD_C64, 4096, 1 << 20),                  # N < 1
+                dd.dd_desc(1024, 4, -1.0, dd.DD_C64, 4096, 1 << 20),              # T <= 0
+                dd.dd_desc(1024, 4, 1.0, 9, 4096, 1 << 20),                       # dtype
+                dd.dd_desc(1024, 4, 1.0, dd.DD_C64, None, 1 << 20),               # null x
+                dd.dd_desc(1024, 4, 1.0, dd.DD_C64, 4100, 1 << 20),               # misaligned x
+                dd.dd_desc(1024, 4, 1.0, dd.DD_C64, 4096, 4096 + 8)]:             # x and X overlap
+        assert dd._lib.dense_dft_batch_plan(ctypes.byref(h), (dd.dd_desc * 1)(bad), 1, 0) == 1
+    for bad in [dd.dd_desc(1024, 0, 1.0, dd.DD_C64, 4096, 1 << 20),               # alpha < 1
+                dd.dd_desc(7 * 64, 2, 1.0, dd.DD_C64, 4096, 1 << 20)]:            # prime factor 7
+        assert dd._lib.dense_dft_batch_plan(ctypes.byref(h), (dd.dd_desc * 1)(bad), 1, 0) == 2
+    assert dd._lib.dense_dft_batch_exec(None, None) == 1
+    assert dd._lib.dense_dft_batch_destroy(None) == 1
