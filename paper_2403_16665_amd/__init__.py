@@ -115,7 +115,7 @@ class Plan:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:
-            Plan._destroy(h)
+            self._destroy(h)
             self.handle = None
 
 
@@ -195,7 +195,7 @@ class Batch:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:
-            Batch._destroy(h)
+            self._destroy(h)
             self.handle = None
 
 

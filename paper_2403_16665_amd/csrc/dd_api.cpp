@@ -232,7 +232,8 @@ dd_status dense_dft_plan(dd_plan_t* out, int64_t N, int32_t alpha, double T, int
     p->p1_njg = (alpha + jg - 1) / jg;
     // stage the block's pre-twiddles in LDS when they take at most 16 KiB
     const size_t pre_bytes = (size_t)jg * N1 * cx_bytes(p);
-    p->p1_pre_lds = pre_bytes <= 16 * 1024 ? 1 : 0;
+    p->p1_pre_lds = pre_bytes <= 16 * 1024 &&
+                    lds_pass1((int)N1, g1.lines, p->rbytes, jg * (int)N1) <= (size_t)LDS_PASS_MAX ? 1 : 0;
     p->p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, p->p1_pre_lds ? jg * (int)N1 : 0);
     p->ws_bytes = (size_t)chunk * per_sig;
   }

@@ -59,15 +59,17 @@ __device__ __forceinline__ void run_pass2(const BatchItem* __restrict__ items, i
   body_pass2<float, L, batch_lines(L)>(it.Y, it.X, a, sub, smem, tid);
 }
 
-// Persistent queue over tasks [first, first + count): every block takes the
-// next task until the queue is empty.  No task of a launch depends on another
-// task of the same launch (pass-2 tasks run in a second launch), so no block
-// ever waits for another.
+// Persistent queue over the tasks of launch `which` (0: single-pass and
+// pass-1 tasks, 1: pass-2 tasks): every block takes the next task until the
+// queue is empty.  No task of a launch depends on another task of the same
+// launch, so no block ever waits for another.
 __global__ __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_batch(
-    const BatchItem* __restrict__ items, const BatchTask* __restrict__ tasks, int first, int count,
+    const BatchItem* __restrict__ items, const BatchMeta* __restrict__ meta, int which,
     unsigned* __restrict__ head) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_task;
+  const int nitems = meta->nitems;
+  const int count = which ? meta->n_second : meta->n_first;
   for (;;) {
     if (threadIdx.x == 0) s_task = (int)atomicAdd(head, 1u);
     __syncthreads();
@@ -76,28 +78,38 @@ __global__ __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(2
     const int ti = __builtin_amdgcn_readfirstlane(s_task);
     __syncthreads();  // every thread has read s_task before thread 0 overwrites it
     if (ti >= count) break;
-    const BatchTask tk = tasks[first + ti];
+    // item: the last k with t[k] <= ti (empty ranges are skipped by "last")
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      const int tm = which ? items[mid].t2 : items[mid].t1;
+      if (tm <= ti) lo = mid;
+      else hi = mid - 1;
+    }
+    const int k = lo;
+    const int sub = ti - (which ? items[k].t2 : items[k].t1);
+    const int code = which ? items[k].code2 : items[k].code1;
     // The thread index passes through an opaque move every iteration, so that
     // no code path's thread-dependent address arithmetic is hoisted out of
     // the task loop (hoisted, the invariants of all paths stay live at once).
     int tid;
     asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
-    switch (tk.w) {
-#define DD_S(LL)                                   \
-  case batch_code(BK_SINGLE, LL):                  \
-    run_single<LL>(items, tk.x, tk.z, smem, tid);  \
+    switch (code) {
+#define DD_S(LL)                                  \
+  case batch_code(BK_SINGLE, LL):                 \
+    run_single<LL>(items, k, sub, smem, tid);     \
     break;
       DD_BATCH_SINGLE(DD_S)
 #undef DD_S
-#define DD_P1(LL)                                  \
-  case batch_code(BK_PASS1, LL):                   \
-    run_pass1<LL>(items, tk.x, tk.z, smem, tid);   \
+#define DD_P1(LL)                                 \
+  case batch_code(BK_PASS1, LL):                  \
+    run_pass1<LL>(items, k, sub, smem, tid);      \
     break;
       DD_BATCH_P1(DD_P1)
 #undef DD_P1
-#define DD_P2(LL)                                  \
-  case batch_code(BK_PASS2, LL):                   \
-    run_pass2<LL>(items, tk.x, tk.z, smem, tid);   \
+#define DD_P2(LL)                                 \
+  case batch_code(BK_PASS2, LL):                  \
+    run_pass2<LL>(items, k, sub, smem, tid);      \
     break;
       DD_BATCH_P2(DD_P2)
 #undef DD_P2
@@ -107,8 +119,8 @@ __global__ __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(2
   }
 }
 
-hipError_t launch_batch(const BatchItem* items, const BatchTask* tasks, int n_first, int n_second, unsigned* ctl,
-                        int grid1, int grid2, size_t lds, hipStream_t s) {
+hipError_t launch_batch(const BatchItem* items, const BatchMeta* meta, unsigned* ctl, int grid1, int grid2,
+                        size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -117,17 +129,11 @@ hipError_t launch_batch(const BatchItem* items, const BatchTask* tasks, int n_fi
                             (int)lds);
     if (e != hipSuccess) return e;
   }
-  if (n_first > 0) {
-    hipLaunchKernelGGL(k_batch, dim3(grid1), dim3(BATCH_THREADS), lds, s, items, tasks, 0, n_first, ctl);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (n_second > 0) {
-    hipLaunchKernelGGL(k_batch, dim3(grid2), dim3(BATCH_THREADS), lds, s, items, tasks, n_first, n_second,
-                       ctl + 1);
-    e = hipGetLastError();
-  }
-  return e;
+  hipLaunchKernelGGL(k_batch, dim3(grid1), dim3(BATCH_THREADS), lds, s, items, meta, 0, ctl);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch, dim3(grid2), dim3(BATCH_THREADS), lds, s, items, meta, 1, ctl + 1);
+  return hipGetLastError();
 }
 
 int batch_max_blocks_per_cu(size_t lds) {

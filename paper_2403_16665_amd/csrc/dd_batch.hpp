@@ -21,7 +21,7 @@ constexpr int BATCH_LDS_MAX = 64 * 1024;
 // Lengths compiled into the batch kernel, per kind.
 #define DD_BATCH_SINGLE(X) \
   X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(384) X(768) X(1536) X(3072) X(320) X(640) X(1280) X(2560)
-#define DD_BATCH_P1(X) X(32) X(64) X(128) X(256) X(512) X(48) X(96) X(192) X(384) X(40) X(80) X(160) X(320)
+#define DD_BATCH_P1(X) X(16) X(32) X(64) X(128) X(256) X(512) X(24) X(48) X(96) X(192) X(384) X(20) X(40) X(80) X(160) X(320)
 #define DD_BATCH_P2(X) X(32) X(64) X(128) X(256) X(512)
 
 enum BatchKind { BK_SINGLE = 0, BK_PASS1 = 1, BK_PASS2 = 2 };
@@ -62,14 +62,22 @@ struct BatchItem {
   int lines1, ntile1, jgroup, njg, pre_lds;  // one pass: lines1 = signals per block (1)
   int ntile2;
   int p1_tasks;           // pass-1 tasks of the item
-  int code1, code2;       // code paths: single or pass 1; pass 2
+  int code1, code2;       // code paths: single or pass 1; pass 2 (-1: one pass)
+  int t1, t2;             // index of the item's first task in launch 1 / launch 2
   float scale;            // T / N
+};
+
+// Per-execution counts, read by the kernels from device memory (so that one
+// captured graph serves batches of any composition).
+struct BatchMeta {
+  int nitems;             // items in the table, ordered by t1 (and t2)
+  int n_first;            // tasks of launch 1: single-pass signals and pass-1 tiles
+  int n_second;           // tasks of launch 2: pass-2 row blocks
   int pad_;
 };
 
-// Task: x = item, y = kind, z = block index within the item's pass, w = code.
-using BatchTask = int4;
-
+// Item k owns tasks [t1[k], t1[k+1]) of launch 1 and [t2[k], t2[k+1]) of
+// launch 2; a block maps a task index to its item by binary search.
 // Control words: [0] queue head of the first launch, [1] of the second.
 
 }  // namespace dd

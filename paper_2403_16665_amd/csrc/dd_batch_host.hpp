@@ -1,0 +1,172 @@
+// dd_batch_host.hpp -- host-side construction of batch descriptors, shared by
+// the batch API (dd_batch_api.cpp) and the request server (dd_serve.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+
+#include "../../include/dense_dft.h"
+#include "dd_batch.hpp"
+#include "dd_host.hpp"
+
+namespace dd {
+
+struct Sched {
+  bool single = false;
+  int N1 = 0, N2 = 1;
+};
+
+// Device twiddle tables of one (N, alpha) schedule class, FP32 rounded from FP64.
+struct ClassTables {
+  Sched sc;
+  void* twL1 = nullptr;
+  void* twPre = nullptr;
+  void* twQ = nullptr;
+  void* twPost = nullptr;
+  void* twL2 = nullptr;
+};
+
+inline size_t batch_in_elem(dd_dtype t) { return t == DD_F32 ? 4 : t == DD_C128 ? 16 : 8; }
+inline size_t batch_out_elem(dd_dtype t) { return (t == DD_F64 || t == DD_C128) ? 16 : 8; }
+
+// Validation of one signal descriptor (the plan's rules, plus pointers).
+inline dd_status batch_check_desc(const dd_desc& d) {
+  if (d.N < 1 || !(d.T > 0.0) || !std::isfinite(d.T)) return DD_ERR_INVALID;
+  if (d.dtype != DD_F32 && d.dtype != DD_C64 && d.dtype != DD_F64 && d.dtype != DD_C128) return DD_ERR_INVALID;
+  if (!d.x || !d.X) return DD_ERR_INVALID;
+  if ((uintptr_t)d.x % batch_in_elem(d.dtype) || (uintptr_t)d.X % batch_out_elem(d.dtype)) return DD_ERR_INVALID;
+  if (d.alpha < 1) return DD_ERR_UNSUPPORTED;
+  if ((int64_t)d.alpha * d.N > ((int64_t)1 << 31)) return DD_ERR_UNSUPPORTED;
+  if (!is_smooth(d.N)) return DD_ERR_UNSUPPORTED;
+  const uintptr_t x0 = (uintptr_t)d.x, x1 = x0 + (size_t)d.N * batch_in_elem(d.dtype);
+  const uintptr_t y0 = (uintptr_t)d.X, y1 = y0 + (size_t)d.alpha * d.N * batch_out_elem(d.dtype);
+  if (x0 < y1 && y0 < x1) return DD_ERR_INVALID;
+  return DD_OK;
+}
+
+// Schedule of one FP32 signal in the batch kernel: one pass when its
+// spectrum fits one block's LDS, else the most balanced N1 x N2 of the
+// compiled pass lengths (N1 <= N2 on ties).  False: not runnable there.
+inline bool batch_schedule(int64_t N, int alpha, Sched* out) {
+  if (N <= 4096 && batch_code(BK_SINGLE, (int)N) >= 0 &&
+      lds_single((int)N, 1, alpha, 4) <= (size_t)BATCH_LDS_MAX) {
+    out->single = true;
+    out->N1 = (int)N;
+    out->N2 = 1;
+    return true;
+  }
+  int best = 1 << 30;
+  bool found = false;
+  for (int n2 = 16; n2 <= 512; n2 *= 2) {
+    if (N % n2 || batch_code(BK_PASS2, n2) < 0) continue;
+    const int64_t n1 = N / n2;
+    if (n1 > 512 || batch_code(BK_PASS1, (int)n1) < 0) continue;
+    const int score = std::abs(ilog2(n1) - ilog2(n2)) * 2 + (n1 > n2 ? 1 : 0);
+    if (score < best) {
+      best = score;
+      out->single = false;
+      out->N1 = (int)n1;
+      out->N2 = n2;
+      found = true;
+    }
+  }
+  return found;
+}
+
+// Whether a descriptor runs in the batch kernel (FP32 input, compiled lengths).
+inline bool batch_kernel_ok(const dd_desc& d, Sched* sc) {
+  return (d.dtype == DD_F32 || d.dtype == DD_C64) && batch_schedule(d.N, d.alpha, sc);
+}
+
+inline size_t batch_scratch_bytes(const dd_desc& d, const Sched& sc) {
+  return sc.single ? 0 : (size_t)d.alpha * d.N * 8;
+}
+
+inline void free_class_tables(ClassTables& ct) {
+  void* ts[] = {ct.twL1, ct.twPre, ct.twQ, ct.twPost, ct.twL2};
+  for (void* t : ts)
+    if (t) (void)hipFree(t);
+  ct = ClassTables{};
+}
+
+// Tables of the class of (N, alpha) with schedule sc, generated on stream s.
+inline dd_status make_class_tables(int64_t N, int alpha, const Sched& sc, bool fp32tw, hipStream_t s,
+                                   ClassTables* ct) {
+  ct->sc = sc;
+  const int64_t M = (int64_t)alpha * N;
+  dd_status st = make_stage_table(&ct->twL1, sc.N1, false, fp32tw, s);
+  if (st == DD_OK) st = make_table(&ct->twPre, alpha, sc.N1, (int64_t)alpha * sc.N1, false, fp32tw, s);
+  if (st == DD_OK && !sc.single) {
+    st = make_table(&ct->twQ, alpha, sc.N2, M, false, fp32tw, s);
+    if (st == DD_OK) st = make_table(&ct->twPost, sc.N1, sc.N2, N, false, fp32tw, s);
+    if (st == DD_OK) st = make_stage_table(&ct->twL2, sc.N2, false, fp32tw, s);
+  }
+  if (st != DD_OK) free_class_tables(*ct);
+  return st;
+}
+
+// Fill every field of a descriptor except t1 / t2; Y is its scratch.
+inline void fill_item(BatchItem& it, const dd_desc& d, const ClassTables& ct, cx<float>* Y) {
+  const Sched& sc = ct.sc;
+  std::memset(&it, 0, sizeof(it));
+  it.x = d.x;
+  it.X = static_cast<cx<float>*>(d.X);
+  it.Y = Y;
+  it.twL1 = static_cast<const cx<float>*>(ct.twL1);
+  it.twPre = static_cast<const cx<float>*>(ct.twPre);
+  it.twQ = static_cast<const cx<float>*>(ct.twQ);
+  it.twPost = static_cast<const cx<float>*>(ct.twPost);
+  it.twL2 = static_cast<const cx<float>*>(ct.twL2);
+  it.N = d.N;
+  it.N1 = sc.N1;
+  it.N2 = sc.N2;
+  it.alpha = d.alpha;
+  it.real = d.dtype == DD_F32 ? 1 : 0;
+  it.scale = (float)(d.T / (double)d.N);
+  if (sc.single) {
+    it.lines1 = 1;
+    it.p1_tasks = 1;
+    it.code1 = batch_code(BK_SINGLE, sc.N1);
+    it.code2 = -1;
+  } else {
+    const int C = batch_lines(sc.N1), RB = batch_lines(sc.N2);
+    it.lines1 = C;
+    it.ntile1 = (sc.N2 + C - 1) / C;
+    it.jgroup = d.alpha;
+    it.njg = 1;
+    it.pre_lds = (size_t)d.alpha * sc.N1 * 8 <= 16 * 1024 ? 1 : 0;
+    it.ntile2 = (d.alpha * sc.N1 + RB - 1) / RB;
+    it.p1_tasks = it.ntile1 * it.njg;
+    it.code1 = batch_code(BK_PASS1, sc.N1);
+    it.code2 = batch_code(BK_PASS2, sc.N2);
+  }
+}
+
+// LDS bytes the item's tasks need.
+inline size_t item_lds(const BatchItem& it) {
+  if (it.code2 < 0) return lds_single(it.N1, 1, it.alpha, 4);
+  const size_t p1 = (size_t)pass1_lds_elems(it.N1, batch_lines(it.N1), it.pre_lds ? it.alpha * it.N1 : 0) * 8;
+  return std::max(p1, lds_pass2(it.N2, batch_lines(it.N2), 4));
+}
+
+// Task offsets of items already in queue order; fills the counts of meta.
+inline void assign_task_offsets(BatchItem* items, int n, BatchMeta* meta) {
+  int t1 = 0, t2 = 0;
+  for (int k = 0; k < n; ++k) {
+    items[k].t1 = t1;
+    items[k].t2 = t2;
+    t1 += items[k].p1_tasks;
+    t2 += items[k].code2 < 0 ? 0 : items[k].ntile2;
+  }
+  meta->nitems = n;
+  meta->n_first = t1;
+  meta->n_second = t2;
+  meta->pad_ = 0;
+}
+
+}  // namespace dd

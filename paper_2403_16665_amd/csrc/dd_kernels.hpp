@@ -67,38 +67,47 @@ struct AnyIn {
   }
 };
 
-// Launch geometry shared by host and device: lines per block so that the
-// block has at most `max_threads` threads and its line data fits `lds_budget`.
-constexpr int LDS_BUDGET = 64 * 1024;
+// LDS elements of pass 1 for a tile of C columns (host and device): the
+// exchange buffer, the stage twiddles and `pre` staged pre-twiddles.
+__host__ __device__ constexpr int pass1_lds_elems(int L, int C, int pre) {
+  return L * C + (L / 16 + 1) * 8 + line_tw_size(make_line_plan(L)) + pre;
+}
+
+// LDS elements of pass 2 for RB rows: the row exchange buffers, reused as the
+// staging buffer of the transposed store.
+__host__ __device__ constexpr int pass2_lds_elems(int L, int RB) {
+  return RB * (L + L / 16 + 1) > L * (RB + 1) ? RB * (L + L / 16 + 1) : L * (RB + 1);
+}
+
+// LDS of one block of a pass kernel may take all of a CU's 160 KiB: the wider
+// the tile, the longer the contiguous runs of its scattered stores.
+constexpr int LDS_PASS_MAX = 160 * 1024;
 
 constexpr int line_threads(int L) { return L / make_line_plan(L).EPT; }
 
+// Launch geometry shared by host and device.
 template <int L, int RBYTES>
 struct Geom {
   static constexpr int TL = line_threads(L);
   static constexpr int CX = 2 * RBYTES;
-  static constexpr int cap_lds(int lines) {
-    while (lines > 1 && lines * (L + L / 16 + 1) * CX > LDS_BUDGET) lines /= 2;
-    return lines;
+  static constexpr int pass_lds(int lines) {
+    return CX * (pass1_lds_elems(L, lines, 0) > pass2_lds_elems(L, lines) ? pass1_lds_elems(L, lines, 0)
+                                                                           : pass2_lds_elems(L, lines));
   }
-  // pass 1 / pass 2: aim for 16 lines, at most 1024 threads, LDS within budget
+  // pass 1 / pass 2: aim for 16 lines, at most 512 threads (so that a wave
+  // may hold 256 VGPRs), LDS within a CU
   static constexpr int lines_pass() {
     int l = 16;
     if (TL * l < 256) l = 256 / TL;
-    while (l > 1 && TL * l > 1024) l /= 2;
-    return cap_lds(l);
+    while (l > 1 && TL * l > 512) l /= 2;
+    while (l > 1 && pass_lds(l) > LDS_PASS_MAX) l /= 2;
+    return l;
   }
   static constexpr int BLOCK_PASS = TL * lines_pass();
   // single pass: up to 256 threads (one line if TL >= 256)
   static constexpr int lines_single() { return TL >= 256 ? 1 : 256 / TL; }
   static constexpr int BLOCK_SINGLE = TL * lines_single();
 };
-
-// LDS elements of pass 1 for a tile of C columns (host and device): the
-// exchange buffer, the stage twiddles and `pre` staged pre-twiddles.
-__host__ __device__ constexpr int pass1_lds_elems(int L, int C, int pre) {
-  return L * C + (L / 16 + 1) * 8 + line_tw_size(make_line_plan(L)) + pre;
-}
 
 // ---------------------------------------------------------------------------
 // Block bodies.  `bid` is the block's index in its launch (or the task index
@@ -280,6 +289,18 @@ __device__ __forceinline__ void body_pass2(const cx<R>* __restrict__ Y, cx<R>* _
 // ---------------------------------------------------------------------------
 // Standalone kernels (one launch per pass).
 // ---------------------------------------------------------------------------
+
+// The blocks of a launch are dealt to the 8 XCDs in turn, each XCD with its
+// own L2.  Renumbered so that every XCD takes a contiguous range of tiles,
+// neighbouring tiles, which share cache lines of input and output, meet in
+// one L2 (the blocks beyond the last full round of 8 keep their index).
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t bid, int64_t nblocks) {
+  constexpr int XCDS = 8;
+  const int64_t per = nblocks / XCDS;
+  if (bid >= per * XCDS) return bid;
+  return (bid % XCDS) * per + bid / XCDS;
+}
+
 template <typename R, typename In, int L, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_single(const In* __restrict__ x, cx<R>* __restrict__ X,
                                                   DenseArgs<R> a) {
@@ -292,7 +313,8 @@ __global__ __launch_bounds__(C * (L / make_line_plan(L).EPT)) void k_pass1(const
                                                                           cx<R>* __restrict__ Y,
                                                                           DenseArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  body_pass1<R, PtrIn<R, In>, L, C>(PtrIn<R, In>{x}, Y, a, blockIdx.x, smem_raw, threadIdx.x);
+  body_pass1<R, PtrIn<R, In>, L, C>(PtrIn<R, In>{x}, Y, a, xcd_contiguous(blockIdx.x, gridDim.x), smem_raw,
+                                    threadIdx.x);
 }
 
 template <typename R, int L, int RB>
@@ -300,7 +322,7 @@ __global__ __launch_bounds__(RB * (L / make_line_plan(L).EPT)) void k_pass2(cons
                                                                            cx<R>* __restrict__ X,
                                                                            DenseArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  body_pass2<R, L, RB>(Y, X, a, blockIdx.x, smem_raw, threadIdx.x);
+  body_pass2<R, L, RB>(Y, X, a, xcd_contiguous(blockIdx.x, gridDim.x), smem_raw, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

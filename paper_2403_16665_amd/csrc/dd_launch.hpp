@@ -55,11 +55,12 @@ DD_DECL_LAUNCHERS(double)
 #undef DD_DECL_LAUNCHERS
 
 struct BatchItem;
+struct BatchMeta;
 // Persistent batch (dd_batch.hip): a reset of the two queue heads in ctl,
-// then two launches of the queue kernel, over tasks [0, n_first) (single-pass
-// and pass-1 tasks) and [n_first, n_first + n_second) (pass-2 tasks).
-hipError_t launch_batch(const BatchItem* items, const int4* tasks, int n_first, int n_second, unsigned* ctl,
-                        int grid1, int grid2, size_t lds, hipStream_t s);
+// then the two launches of the queue kernel (single-pass and pass-1 tasks,
+// then pass-2 tasks), with counts read from `meta` in device memory.
+hipError_t launch_batch(const BatchItem* items, const BatchMeta* meta, unsigned* ctl, int grid1, int grid2,
+                        size_t lds, hipStream_t s);
 int batch_max_blocks_per_cu(size_t lds);
 
 // LDS bytes of each kernel for a given length and lines per block.
@@ -70,9 +71,7 @@ inline size_t lds_pass1(int L, int lines, int rbytes, int pre_elems) {
   return (size_t)pass1_lds_elems(L, lines, pre_elems) * 2 * rbytes;
 }
 inline size_t lds_pass2(int L, int lines, int rbytes) {
-  size_t a = (size_t)lines * (L + L / 16 + 1);
-  size_t b = (size_t)L * (lines + 1);
-  return (a > b ? a : b) * 2 * rbytes;
+  return (size_t)pass2_lds_elems(L, lines) * 2 * rbytes;
 }
 
 // Kernel launch with the dynamic-LDS attribute raised when needed.
