@@ -74,6 +74,10 @@ typedef enum dd_status {
  *                    double-precision dtypes. */
 #define DD_TWIDDLE_FP64 0u
 #define DD_TWIDDLE_FP32 1u
+/* Plan flag: allocate no default workspace; every execution of a two-pass
+ * plan must then pass one (for callers that carve workspaces from a pool of
+ * their own). */
+#define DD_NO_WORKSPACE 2u
 
 typedef struct dd_plan *dd_plan_t;
 
@@ -91,13 +95,14 @@ typedef struct dd_plan *dd_plan_t;
  *   T      : finite, > 0.
  *   batch  : number of signals, >= 1, batch*alpha*N must fit int64.
  *   dtype  : input dtype (see above).
- *   flags  : DD_TWIDDLE_FP64 or DD_TWIDDLE_FP32.
+ *   flags  : DD_TWIDDLE_FP64 or DD_TWIDDLE_FP32, optionally | DD_NO_WORKSPACE.
  * Errors: DD_ERR_INVALID, DD_ERR_UNSUPPORTED, DD_ERR_NOMEM, DD_ERR_DEVICE. */
 dd_status dense_dft_plan(dd_plan_t *out, int64_t N, int32_t alpha, double T,
                          int64_t batch, dd_dtype dtype, uint32_t flags);
 
 /* Bytes of device scratch one execution needs (0 for single-pass plans).
- * The plan owns a default workspace of this size. */
+ * The plan owns a default workspace of this size unless it was created with
+ * DD_NO_WORKSPACE. */
 dd_status dense_dft_workspace_size(dd_plan_t plan, size_t *bytes);
 
 /* Enqueue the transform of all `batch` signals of the plan on `stream`.
@@ -107,7 +112,8 @@ dd_status dense_dft_workspace_size(dd_plan_t plan, size_t *bytes);
  *               to 8 / 16 bytes; must not overlap x.
  *   workspace : device scratch of dense_dft_workspace_size() bytes, or NULL
  *               to use the plan's own (then executions of this plan must not
- *               overlap in time).
+ *               overlap in time; DD_ERR_INVALID for a two-pass plan made
+ *               with DD_NO_WORKSPACE).
  *   stream    : hipStream_t, NULL for the default stream.
  * Errors: DD_ERR_INVALID (null / misaligned / overlapping pointers),
  *         DD_ERR_DEVICE (kernel launch failed). */
@@ -161,8 +167,8 @@ typedef struct dd_batch *dd_batch_t;
  * twiddle tables of every distinct (N, alpha) on the GPU in FP64 (rounded
  * once; DD_TWIDDLE_FP32 as for plans), allocate the scratch of the two-pass
  * signals, and build the device work list: one task per block-sized piece
- * (a single-pass signal, a pass-1 column tile, a pass-2 row block), queued
- * so that every task depends only on tasks queued before it.  FP32/complex64
+ * (a single-pass signal, a pass-1 column tile, a pass-2 row block), with
+ * the signals ordered largest spectrum first.  FP32/complex64
  * signals of the compiled lengths run in the persistent kernel; the others
  * (FP64 dtypes, other lengths) run as plain per-signal executions after it.
  * The descriptors are copied; the caller keeps ownership of x and X.
@@ -207,6 +213,108 @@ dd_status dense_dft_batch_destroy(dd_batch_t b);
 /* Convenience: plan, execute on `stream`, synchronise it, and free. */
 dd_status dense_dft_exec_many(const dd_desc *descs, int32_t count,
                               void *stream);
+
+/* ---- Serving: continuous batching of requests as they arrive ----
+ *
+ * A server keeps on one device: a scratch pool of hbm_budget_bytes, the
+ * twiddle tables of every (N, alpha) class it has met (and plain plans for
+ * requests outside the batch kernel), and max_inflight execution slots, each
+ * with a stream, an event and a HIP graph of the persistent batch launch
+ * captured once at creation (its descriptor table is re-read from pinned
+ * host memory at every replay, so one graph serves batches of any mix).
+ * A scheduler thread takes queued requests in arrival order whenever a slot
+ * is free, as many as the batch size and the memory budget admit, and
+ * launches them as one batch while earlier batches still run on the other
+ * slots.  A request's footprint is its input and output bytes plus its
+ * scratch; the footprints of admitted, unfinished requests never sum past
+ * hbm_budget_bytes.  Each request is the transform of one dd_desc (the
+ * problem of Section 2 for one signal); x and X are the caller's device
+ * buffers and must stay allocated and untouched until the request is done.
+ * The server's streams are not ordered after any of the caller's: x must
+ * hold its samples (the stream that wrote it synchronised) when submitted,
+ * and X is complete once its result reports done.
+ * Times are host steady-clock nanoseconds (dense_dft_clock_ns). */
+
+typedef struct dd_server *dd_server_t;
+
+#define DD_SERVE_BATCHED 0
+#define DD_SERVE_PLAIN 1
+
+typedef struct dd_server_cfg {
+    int32_t device;           /* HIP device ordinal */
+    int32_t mode;             /* DD_SERVE_BATCHED, or DD_SERVE_PLAIN: every request runs
+                                 alone as a plain execution (the per-request baseline) */
+    size_t hbm_budget_bytes;  /* footprint bound and scratch pool size; 0 -> 8 GiB */
+    int32_t max_inflight;     /* slots; 0 -> 2 (batched) or 8 (plain); at most 64 */
+    int32_t max_batch;        /* requests per batch; 0 -> 256; at most 4096 (plain: 1) */
+    int32_t max_queue;        /* queued, not yet admitted requests; 0 -> 65536 */
+    uint32_t flags;           /* DD_TWIDDLE_FP64 or DD_TWIDDLE_FP32 */
+    void *hip_stream;         /* NULL: a stream per slot; else every slot runs on this one */
+} dd_server_cfg;
+
+typedef struct dd_result {
+    dd_status status;         /* DD_OK, or the error its execution met */
+    int32_t batch_requests;   /* requests in the batch it ran in */
+    uint64_t t_arrival_ns;    /* submission time, or the caller's arrival stamp */
+    uint64_t t_start_ns;      /* its batch was launched */
+    uint64_t t_done_ns;       /* the scheduler saw its batch complete */
+} dd_result;
+
+typedef struct dd_server_stats {
+    uint64_t submitted;
+    uint64_t completed;
+    uint64_t batches;             /* launches (batched: one per batch; plain: one per request) */
+    uint64_t kernel_requests;     /* run in the persistent batch kernel */
+    uint64_t fallback_requests;   /* run as plain executions */
+    int32_t max_batch_seen;
+    int32_t classes;              /* (N, alpha) classes with resident tables */
+    size_t pool_bytes;
+    size_t peak_footprint;
+} dd_server_stats;
+
+/* Create a server on cfg->device (allocates the pool, slots and graphs,
+ * starts the scheduler thread).  Errors: DD_ERR_INVALID (null pointers,
+ * fields out of range), DD_ERR_DEVICE (no such device, HIP failure),
+ * DD_ERR_NOMEM. */
+dd_status dense_dft_server_create(const dd_server_cfg *cfg, dd_server_t *out);
+
+/* Make the tables (or plan) of one request class resident now rather than
+ * at its first admission.  Errors as dense_dft_plan, DD_ERR_CLOSED. */
+dd_status dense_dft_server_warm(dd_server_t s, int64_t N, int32_t alpha, double T,
+                                dd_dtype dtype);
+
+/* Queue one request without blocking; *ticket identifies it.  The arrival
+ * time is the call's time (dense_dft_submit) or t_arrival_ns, e.g. the time
+ * an open-loop generator scheduled it (dense_dft_submit_at).
+ * Errors: DD_ERR_INVALID (bad descriptor, as dense_dft_batch_plan),
+ * DD_ERR_UNSUPPORTED, DD_ERR_TOO_LARGE (its footprint exceeds the budget),
+ * DD_ERR_BUSY (max_queue requests already queued), DD_ERR_CLOSED. */
+dd_status dense_dft_submit(dd_server_t s, const dd_desc *req, uint64_t *ticket);
+dd_status dense_dft_submit_at(dd_server_t s, const dd_desc *req, uint64_t t_arrival_ns,
+                              uint64_t *ticket);
+
+/* Result of a request: DD_OK with *r filled once it is done (the ticket is
+ * then retired), DD_ERR_BUSY while it is queued or running,
+ * DD_ERR_INVALID for an unknown or retired ticket. */
+dd_status dense_dft_poll(dd_server_t s, uint64_t ticket, dd_result *r);
+
+/* As dense_dft_poll, but blocks until the request is done or timeout_us
+ * microseconds pass (negative: no limit) -> DD_ERR_TIMEOUT. */
+dd_status dense_dft_wait(dd_server_t s, uint64_t ticket, int64_t timeout_us, dd_result *r);
+
+/* Hold (paused != 0) or release admission; queued requests wait while held. */
+dd_status dense_dft_server_pause(dd_server_t s, int32_t paused);
+
+/* Counters since creation. */
+dd_status dense_dft_server_stats(dd_server_t s, dd_server_stats *st);
+
+/* Stop accepting requests, run every queued request to completion, stop the
+ * scheduler and free the server's device memory.  Unretired results are
+ * discarded. */
+dd_status dense_dft_server_destroy(dd_server_t s);
+
+/* The host clock of the serving stamps, in nanoseconds. */
+uint64_t dense_dft_clock_ns(void);
 
 /* Static text for a status code. */
 const char *dense_dft_status_string(dd_status status);

@@ -26,6 +26,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 DD_F32, DD_C64, DD_F64, DD_C128 = 0, 1, 2, 3
 DD_TWIDDLE_FP64, DD_TWIDDLE_FP32 = 0, 1
+DD_NO_WORKSPACE = 2
+DD_SERVE_BATCHED, DD_SERVE_PLAIN = 0, 1
 STATUS = {0: "DD_OK", 1: "DD_ERR_INVALID", 2: "DD_ERR_UNSUPPORTED", 3: "DD_ERR_NOMEM",
           4: "DD_ERR_DEVICE", 5: "DD_ERR_BUSY", 6: "DD_ERR_TOO_LARGE", 7: "DD_ERR_TIMEOUT",
           8: "DD_ERR_CLOSED"}
@@ -259,6 +261,147 @@ def dense_dft_exec_many(descs, stream=None) -> None:
         stream = torch.cuda.current_stream().cuda_stream
     arr, n = _desc_array(descs)
     _check(_lib.dense_dft_exec_many(arr, n, _vp(stream)), "dense_dft_exec_many")
+
+
+# --- serving: continuous batching of requests as they arrive ---
+class dd_server_cfg(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("mode", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p)]
+
+
+class dd_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("batch_requests", ctypes.c_int32), ("t_arrival_ns", ctypes.c_uint64),
+                ("t_start_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+class dd_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("kernel_requests", ctypes.c_uint64), ("fallback_requests", ctypes.c_uint64),
+                ("max_batch_seen", ctypes.c_int32), ("classes", ctypes.c_int32), ("pool_bytes", ctypes.c_size_t),
+                ("peak_footprint", ctypes.c_size_t)]
+
+
+_u64 = ctypes.c_uint64
+_lib.dense_dft_server_create.argtypes = [ctypes.POINTER(dd_server_cfg), ctypes.POINTER(_vp)]
+_lib.dense_dft_server_create.restype = ctypes.c_int
+_lib.dense_dft_server_warm.argtypes = [_vp, _i64, ctypes.c_int32, ctypes.c_double, ctypes.c_int]
+_lib.dense_dft_server_warm.restype = ctypes.c_int
+_lib.dense_dft_submit.argtypes = [_vp, ctypes.POINTER(dd_desc), ctypes.POINTER(_u64)]
+_lib.dense_dft_submit.restype = ctypes.c_int
+_lib.dense_dft_submit_at.argtypes = [_vp, ctypes.POINTER(dd_desc), _u64, ctypes.POINTER(_u64)]
+_lib.dense_dft_submit_at.restype = ctypes.c_int
+_lib.dense_dft_poll.argtypes = [_vp, _u64, ctypes.POINTER(dd_result)]
+_lib.dense_dft_poll.restype = ctypes.c_int
+_lib.dense_dft_wait.argtypes = [_vp, _u64, _i64, ctypes.POINTER(dd_result)]
+_lib.dense_dft_wait.restype = ctypes.c_int
+_lib.dense_dft_server_pause.argtypes = [_vp, ctypes.c_int32]
+_lib.dense_dft_server_pause.restype = ctypes.c_int
+_lib.dense_dft_server_stats.argtypes = [_vp, ctypes.POINTER(dd_server_stats)]
+_lib.dense_dft_server_stats.restype = ctypes.c_int
+_lib.dense_dft_server_destroy.argtypes = [_vp]
+_lib.dense_dft_server_destroy.restype = ctypes.c_int
+_lib.dense_dft_clock_ns.argtypes = []
+_lib.dense_dft_clock_ns.restype = _u64
+
+DD_ERR_BUSY, DD_ERR_TOO_LARGE, DD_ERR_TIMEOUT, DD_ERR_CLOSED = 5, 6, 7, 8
+
+
+class Server:
+    """Owning handle of a dd_server_t (destroyed, after draining, when collected)."""
+
+    _destroy = _lib.dense_dft_server_destroy
+
+    def __init__(self, handle, cfg):
+        self.handle = handle
+        self.cfg = cfg
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            self._destroy(h)
+            self.handle = None
+
+
+def dense_dft_server_create(device: int = 0, mode: int = DD_SERVE_BATCHED, hbm_budget_bytes: int = 0,
+                            max_inflight: int = 0, max_batch: int = 0, max_queue: int = 0,
+                            flags: int = DD_TWIDDLE_FP64, hip_stream=None) -> Server:
+    cfg = dd_server_cfg(int(device), int(mode), int(hbm_budget_bytes), int(max_inflight), int(max_batch),
+                        int(max_queue), int(flags), hip_stream)
+    h = _vp()
+    _check(_lib.dense_dft_server_create(ctypes.byref(cfg), ctypes.byref(h)), "dense_dft_server_create")
+    return Server(h, cfg)
+
+
+def dense_dft_server_warm(server: Server, N: int, alpha: int, T: float, dtype: int) -> None:
+    _check(_lib.dense_dft_server_warm(server.handle, int(N), int(alpha), float(T), int(dtype)),
+           "dense_dft_server_warm")
+
+
+def _one_desc(d) -> dd_desc:
+    if isinstance(d, dd_desc):
+        return d
+    N, alpha, T, dtype, x, X = d
+    return dd_desc(int(N), int(alpha), float(T), int(dtype), x.data_ptr(), X.data_ptr())
+
+
+def dense_dft_submit(server: Server, desc, t_arrival_ns: int | None = None) -> int:
+    """Queue one request (N, alpha, T, dtype, x_tensor, X_tensor); returns its ticket.
+    Raises DenseDFTError (status DD_ERR_BUSY / DD_ERR_TOO_LARGE / ...) on refusal."""
+    d = _one_desc(desc)
+    t = _u64()
+    if t_arrival_ns is None:
+        rc = _lib.dense_dft_submit(server.handle, ctypes.byref(d), ctypes.byref(t))
+    else:
+        rc = _lib.dense_dft_submit_at(server.handle, ctypes.byref(d), int(t_arrival_ns), ctypes.byref(t))
+    _check(rc, "dense_dft_submit")
+    return int(t.value)
+
+
+def dense_dft_submit_at(server: Server, desc, t_arrival_ns: int) -> int:
+    """Queue one request stamped with the caller's arrival time (open-loop load)."""
+    return dense_dft_submit(server, desc, t_arrival_ns)
+
+
+def _result_dict(r: dd_result) -> dict:
+    return {"status": int(r.status), "batch_requests": int(r.batch_requests), "t_arrival_ns": int(r.t_arrival_ns),
+            "t_start_ns": int(r.t_start_ns), "t_done_ns": int(r.t_done_ns)}
+
+
+def dense_dft_poll(server: Server, ticket: int):
+    """Result dict once done (the ticket is then retired), None while pending."""
+    r = dd_result()
+    rc = _lib.dense_dft_poll(server.handle, int(ticket), ctypes.byref(r))
+    if rc == DD_ERR_BUSY:
+        return None
+    _check(rc, "dense_dft_poll")
+    return _result_dict(r)
+
+
+def dense_dft_wait(server: Server, ticket: int, timeout_us: int = -1) -> dict:
+    r = dd_result()
+    _check(_lib.dense_dft_wait(server.handle, int(ticket), int(timeout_us), ctypes.byref(r)), "dense_dft_wait")
+    return _result_dict(r)
+
+
+def dense_dft_server_pause(server: Server, paused: bool) -> None:
+    _check(_lib.dense_dft_server_pause(server.handle, 1 if paused else 0), "dense_dft_server_pause")
+
+
+def dense_dft_server_stats(server: Server) -> dict:
+    st = dd_server_stats()
+    _check(_lib.dense_dft_server_stats(server.handle, ctypes.byref(st)), "dense_dft_server_stats")
+    return {name: int(getattr(st, name)) for name, _ in dd_server_stats._fields_}
+
+
+def dense_dft_server_destroy(server: Server) -> None:
+    if server.handle:
+        _check(_lib.dense_dft_server_destroy(server.handle), "dense_dft_server_destroy")
+        server.handle = None
+
+
+def dense_dft_clock_ns() -> int:
+    return int(_lib.dense_dft_clock_ns())
 
 
 # --- torch conveniences (memory allocation only) ---

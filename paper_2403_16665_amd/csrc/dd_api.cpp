@@ -148,7 +148,7 @@ dd_status dense_dft_plan(dd_plan_t* out, int64_t N, int32_t alpha, double T, int
   *out = nullptr;
   if (N < 1 || batch < 1 || !(T > 0.0) || !std::isfinite(T)) return DD_ERR_INVALID;
   if (dtype != DD_F32 && dtype != DD_C64 && dtype != DD_F64 && dtype != DD_C128) return DD_ERR_INVALID;
-  if (flags & ~(uint32_t)DD_TWIDDLE_FP32) return DD_ERR_INVALID;
+  if (flags & ~(uint32_t)(DD_TWIDDLE_FP32 | DD_NO_WORKSPACE)) return DD_ERR_INVALID;
   if (alpha < 1) return DD_ERR_UNSUPPORTED;
   const int64_t M = (int64_t)alpha * N;
   if (M > ((int64_t)1 << 31) || batch > INT64_MAX / M) return DD_ERR_UNSUPPORTED;
@@ -247,7 +247,7 @@ dd_status dense_dft_plan(dd_plan_t* out, int64_t N, int32_t alpha, double T, int
     st = gen_stage_table(p, &p->twL2, (int)p->N2, fp32tw, s);
     if (st == DD_OK) st = gen_table(p, &p->twQ, alpha, p->N2, M, fp32tw, s);
     if (st == DD_OK) st = gen_table(p, &p->twPost, p->N1, p->N2, N, fp32tw, s);
-    if (st == DD_OK) st = hip_status(hipMalloc(&p->ws, p->ws_bytes));
+    if (st == DD_OK && !(flags & DD_NO_WORKSPACE)) st = hip_status(hipMalloc(&p->ws, p->ws_bytes));
   }
   if (st == DD_OK) st = hip_status(hipStreamSynchronize(s));
   if (st != DD_OK) {

@@ -119,16 +119,19 @@ __global__ __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(2
   }
 }
 
+hipError_t batch_set_lds(size_t lds) {
+  // dynamic LDS plus the kernel's static word beyond the default 64 KiB
+  // needs the attribute; it is set outside any stream capture
+  if (lds + 64 <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
 hipError_t launch_batch(const BatchItem* items, const BatchMeta* meta, unsigned* ctl, int grid1, int grid2,
                         size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (lds > 64 * 1024) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
-    if (e != hipSuccess) return e;
-  }
   hipLaunchKernelGGL(k_batch, dim3(grid1), dim3(BATCH_THREADS), lds, s, items, meta, 0, ctl);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -139,6 +139,7 @@ dd_status dense_dft_batch_plan(dd_batch_t* out, const dd_desc* descs, int32_t co
     if (st == DD_OK) st = hip_status(hipMalloc((void**)&b->d_items, sizeof(BatchItem) * nk));
     if (st == DD_OK) st = hip_status(hipMalloc((void**)&b->d_meta, sizeof(BatchMeta)));
     if (st == DD_OK) st = hip_status(hipMalloc((void**)&b->d_ctl, sizeof(unsigned) * 2));
+    if (st == DD_OK) st = hip_status(batch_set_lds(b->lds));
     if (st == DD_OK) {
       hipDeviceProp_t prop;
       st = hip_status(hipGetDeviceProperties(&prop, b->device));

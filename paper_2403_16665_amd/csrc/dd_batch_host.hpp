@@ -34,15 +34,23 @@ struct ClassTables {
 inline size_t batch_in_elem(dd_dtype t) { return t == DD_F32 ? 4 : t == DD_C128 ? 16 : 8; }
 inline size_t batch_out_elem(dd_dtype t) { return (t == DD_F64 || t == DD_C128) ? 16 : 8; }
 
-// Validation of one signal descriptor (the plan's rules, plus pointers).
+// Validation of a signal's shape (the plan's rules).
+inline dd_status batch_check_shape(int64_t N, int alpha, double T, dd_dtype dtype) {
+  if (N < 1 || !(T > 0.0) || !std::isfinite(T)) return DD_ERR_INVALID;
+  if (dtype != DD_F32 && dtype != DD_C64 && dtype != DD_F64 && dtype != DD_C128) return DD_ERR_INVALID;
+  if (alpha < 1) return DD_ERR_UNSUPPORTED;
+  if ((int64_t)alpha * N > ((int64_t)1 << 31)) return DD_ERR_UNSUPPORTED;
+  if (!is_smooth(N)) return DD_ERR_UNSUPPORTED;
+  return DD_OK;
+}
+
+// Validation of one signal descriptor: shape, then pointers (non-null,
+// aligned to the element size, x and X disjoint).
 inline dd_status batch_check_desc(const dd_desc& d) {
-  if (d.N < 1 || !(d.T > 0.0) || !std::isfinite(d.T)) return DD_ERR_INVALID;
-  if (d.dtype != DD_F32 && d.dtype != DD_C64 && d.dtype != DD_F64 && d.dtype != DD_C128) return DD_ERR_INVALID;
   if (!d.x || !d.X) return DD_ERR_INVALID;
+  const dd_status st = batch_check_shape(d.N, d.alpha, d.T, d.dtype);
+  if (st != DD_OK) return st;
   if ((uintptr_t)d.x % batch_in_elem(d.dtype) || (uintptr_t)d.X % batch_out_elem(d.dtype)) return DD_ERR_INVALID;
-  if (d.alpha < 1) return DD_ERR_UNSUPPORTED;
-  if ((int64_t)d.alpha * d.N > ((int64_t)1 << 31)) return DD_ERR_UNSUPPORTED;
-  if (!is_smooth(d.N)) return DD_ERR_UNSUPPORTED;
   const uintptr_t x0 = (uintptr_t)d.x, x1 = x0 + (size_t)d.N * batch_in_elem(d.dtype);
   const uintptr_t y0 = (uintptr_t)d.X, y1 = y0 + (size_t)d.alpha * d.N * batch_out_elem(d.dtype);
   if (x0 < y1 && y0 < x1) return DD_ERR_INVALID;
