@@ -178,15 +178,15 @@ typedef struct dd_batch *dd_batch_t;
 dd_status dense_dft_batch_plan(dd_batch_t *out, const dd_desc *descs,
                                int32_t count, uint32_t flags);
 
-/* Enqueue the whole batch on `stream`: an asynchronous copy of the
- * descriptor table from pinned host memory, a reset of the two queue heads,
- * two launches of the persistent queue kernel (a fixed grid sized to the
- * device's occupancy; its blocks take tasks until the queue is empty): the
- * first runs every single-pass and pass-1 task, the second every pass-2
- * task, so no block waits for another; then the plain executions of the
- * fallback signals.  Nothing synchronises, no
- * memory is allocated and no memset is enqueued, so the call can be captured
- * in a HIP graph; a replay re-reads the descriptor table at replay time.
+/* Enqueue the whole batch on `stream`: a staging kernel that reads the
+ * descriptor table from pinned host memory into device memory and clears the
+ * two queue heads, then the persistent queue kernel (a fixed grid sized to
+ * the device's occupancy; its blocks take tasks until the queue is empty)
+ * over every single-pass and pass-1 task, then, if the batch has two-pass
+ * signals, over every pass-2 task, so no block waits for another; then the
+ * plain executions of the fallback signals.  Nothing synchronises, no memory
+ * is allocated and no memset is enqueued, so the call can be captured in a
+ * HIP graph; a replay re-reads the descriptor table at replay time.
  * Executions of one batch must not overlap in time. */
 dd_status dense_dft_batch_exec(dd_batch_t b, void *stream);
 
@@ -292,6 +292,15 @@ dd_status dense_dft_server_warm(dd_server_t s, int64_t N, int32_t alpha, double 
 dd_status dense_dft_submit(dd_server_t s, const dd_desc *req, uint64_t *ticket);
 dd_status dense_dft_submit_at(dd_server_t s, const dd_desc *req, uint64_t t_arrival_ns,
                               uint64_t *ticket);
+
+/* Open-loop submission of a pre-drawn arrival schedule (load generation,
+ * trace replay): request i is queued at host time t_arrival_ns[i] (the call
+ * spins until then; the times must not decrease) and stamped with that time;
+ * tickets[i] receives its ticket.  Returns once the last is queued, or at
+ * the first refusal, whose status it returns (the statuses of
+ * dense_dft_submit); *submitted is set to the number queued either way. */
+dd_status dense_dft_submit_many_at(dd_server_t s, const dd_desc *reqs, const uint64_t *t_arrival_ns,
+                                   int32_t count, uint64_t *tickets, int32_t *submitted);
 
 /* Result of a request: DD_OK with *r filled once it is done (the ticket is
  * then retired), DD_ERR_BUSY while it is queued or running,

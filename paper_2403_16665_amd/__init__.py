@@ -291,6 +291,9 @@ _lib.dense_dft_submit.argtypes = [_vp, ctypes.POINTER(dd_desc), ctypes.POINTER(_
 _lib.dense_dft_submit.restype = ctypes.c_int
 _lib.dense_dft_submit_at.argtypes = [_vp, ctypes.POINTER(dd_desc), _u64, ctypes.POINTER(_u64)]
 _lib.dense_dft_submit_at.restype = ctypes.c_int
+_lib.dense_dft_submit_many_at.argtypes = [_vp, ctypes.POINTER(dd_desc), ctypes.POINTER(_u64), ctypes.c_int32,
+                                          ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_int32)]
+_lib.dense_dft_submit_many_at.restype = ctypes.c_int
 _lib.dense_dft_poll.argtypes = [_vp, _u64, ctypes.POINTER(dd_result)]
 _lib.dense_dft_poll.restype = ctypes.c_int
 _lib.dense_dft_wait.argtypes = [_vp, _u64, _i64, ctypes.POINTER(dd_result)]
@@ -361,6 +364,18 @@ def dense_dft_submit(server: Server, desc, t_arrival_ns: int | None = None) -> i
 def dense_dft_submit_at(server: Server, desc, t_arrival_ns: int) -> int:
     """Queue one request stamped with the caller's arrival time (open-loop load)."""
     return dense_dft_submit(server, desc, t_arrival_ns)
+
+
+def dense_dft_submit_many_at(server: Server, descs, t_arrival_ns):
+    """Open-loop replay: queue descs[i] at host time t_arrival_ns[i] (non-decreasing,
+    dense_dft_clock_ns scale); returns the tickets.  Blocks until the last is queued."""
+    arr, n = _desc_array(descs)
+    ts = (_u64 * n)(*[int(t) for t in t_arrival_ns])
+    tk = (_u64 * n)()
+    done = ctypes.c_int32()
+    rc = _lib.dense_dft_submit_many_at(server.handle, arr, ts, n, tk, ctypes.byref(done))
+    _check(rc, f"dense_dft_submit_many_at (queued {done.value} of {n})")
+    return [int(t) for t in tk]
 
 
 def _result_dict(r: dd_result) -> dict:

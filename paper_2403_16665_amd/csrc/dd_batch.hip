@@ -4,8 +4,28 @@
 
 namespace dd {
 
-__global__ void k_batch_reset(unsigned* __restrict__ ctl) {
-  if (threadIdx.x < 2) ctl[threadIdx.x] = 0u;
+// Refresh the device copy of a batch's descriptor table from the pinned host
+// table (read over the bus at launch time, so that a captured graph picks up
+// whatever the host wrote before the replay), with the item count clamped to
+// the table's capacity, and clear the two queue heads.
+__global__ __launch_bounds__(256) void k_batch_stage(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                     int cap, unsigned* __restrict__ ctl) {
+  __shared__ int s_n;
+  if (threadIdx.x == 0) {
+    const int n = reinterpret_cast<const BatchMeta*>(src)->nitems;
+    s_n = n < 0 ? 0 : (n > cap ? cap : n);
+  }
+  __syncthreads();
+  const int words = (int)((sizeof(BatchMeta) + sizeof(BatchItem) * (size_t)s_n + 15) / 16);
+  constexpr int META_WORDS = (int)(sizeof(BatchMeta) / 16);
+  for (int i = META_WORDS + blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x)
+    dst[i] = src[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    BatchMeta m = *reinterpret_cast<const BatchMeta*>(src);
+    m.nitems = s_n;
+    *reinterpret_cast<BatchMeta*>(dst) = m;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 2) ctl[threadIdx.x] = 0u;
 }
 
 // One task of each code path.
@@ -70,6 +90,7 @@ __global__ __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(2
   __shared__ int s_task;
   const int nitems = meta->nitems;
   const int count = which ? meta->n_second : meta->n_first;
+  if (nitems <= 0) return;
   for (;;) {
     if (threadIdx.x == 0) s_task = (int)atomicAdd(head, 1u);
     __syncthreads();
@@ -127,14 +148,19 @@ hipError_t batch_set_lds(size_t lds) {
                              (int)lds);
 }
 
-hipError_t launch_batch(const BatchItem* items, const BatchMeta* meta, unsigned* ctl, int grid1, int grid2,
+hipError_t launch_batch(const void* tab_host, void* tab_dev, int cap, unsigned* ctl, int grid1, int grid2,
                         size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, ctl);
+  const int words = (int)(batch_table_bytes(cap) / 16);
+  const int gstage = (words + 1023) / 1024;
+  hipLaunchKernelGGL(k_batch_stage, dim3(gstage), dim3(256), 0, s, static_cast<const uint4*>(tab_host),
+                     static_cast<uint4*>(tab_dev), cap, ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const BatchMeta* meta = static_cast<const BatchMeta*>(tab_dev);
+  const BatchItem* items = batch_table_items(meta);
   hipLaunchKernelGGL(k_batch, dim3(grid1), dim3(BATCH_THREADS), lds, s, items, meta, 0, ctl);
   e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || grid2 <= 0) return e;
   hipLaunchKernelGGL(k_batch, dim3(grid2), dim3(BATCH_THREADS), lds, s, items, meta, 1, ctl + 1);
   return hipGetLastError();
 }

@@ -80,4 +80,15 @@ struct BatchMeta {
 // launch 2; a block maps a task index to its item by binary search.
 // Control words: [0] queue head of the first launch, [1] of the second.
 
+// Descriptor table of one launch: a BatchMeta, then `cap` items; its size is
+// rounded to whole 16-byte words.
+static_assert(sizeof(BatchMeta) == 16, "the table header is one 16-byte word");
+__host__ __device__ constexpr size_t batch_table_bytes(int cap) {
+  return (sizeof(BatchMeta) + sizeof(BatchItem) * (size_t)cap + 15) / 16 * 16;
+}
+__host__ __device__ inline const BatchItem* batch_table_items(const BatchMeta* m) {
+  return reinterpret_cast<const BatchItem*>(m + 1);
+}
+__host__ __device__ inline BatchItem* batch_table_items(BatchMeta* m) { return reinterpret_cast<BatchItem*>(m + 1); }
+
 }  // namespace dd

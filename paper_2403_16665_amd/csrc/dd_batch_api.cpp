@@ -29,11 +29,7 @@ struct dd_batch {
   std::vector<int> fb;                     // descriptor index of each fallback signal
   std::vector<dd_plan_t> fb_plans;
   std::map<std::pair<int64_t, int>, ClassTables> classes;
-  BatchItem* h_items = nullptr;            // pinned host copy of the descriptor table
-  BatchMeta* h_meta = nullptr;
-  BatchItem* d_items = nullptr;
-  BatchMeta* d_meta = nullptr;
-  unsigned* d_ctl = nullptr;
+  BatchTable tab;                          // descriptor table (queue order)
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
   size_t lds = 0;
@@ -48,16 +44,8 @@ void batch_free(dd_batch* b) {
   b->fb_plans.clear();
   for (auto& kv : b->classes) free_class_tables(kv.second);
   b->classes.clear();
-  if (b->h_items) (void)hipHostFree(b->h_items);
-  if (b->h_meta) (void)hipHostFree(b->h_meta);
-  void* ds[] = {b->d_items, b->d_meta, b->d_ctl, b->scratch};
-  for (void* d : ds)
-    if (d) (void)hipFree(d);
-  b->h_items = nullptr;
-  b->h_meta = nullptr;
-  b->d_items = nullptr;
-  b->d_meta = nullptr;
-  b->d_ctl = nullptr;
+  free_table(b->tab);
+  if (b->scratch) (void)hipFree(b->scratch);
   b->scratch = nullptr;
 }
 
@@ -130,15 +118,11 @@ dd_status dense_dft_batch_plan(dd_batch_t* out, const dd_desc* descs, int32_t co
     }
     BatchMeta meta;
     assign_task_offsets(items.data(), nk, &meta);
-    if (st == DD_OK) st = hip_status(hipHostMalloc((void**)&b->h_items, sizeof(BatchItem) * nk, hipHostMallocDefault));
-    if (st == DD_OK) st = hip_status(hipHostMalloc((void**)&b->h_meta, sizeof(BatchMeta), hipHostMallocDefault));
+    if (st == DD_OK) st = alloc_table(b->tab, nk);
     if (st == DD_OK) {
-      std::memcpy(b->h_items, items.data(), sizeof(BatchItem) * nk);
-      *b->h_meta = meta;
+      std::memcpy(b->tab.items(), items.data(), sizeof(BatchItem) * nk);
+      *b->tab.host = meta;
     }
-    if (st == DD_OK) st = hip_status(hipMalloc((void**)&b->d_items, sizeof(BatchItem) * nk));
-    if (st == DD_OK) st = hip_status(hipMalloc((void**)&b->d_meta, sizeof(BatchMeta)));
-    if (st == DD_OK) st = hip_status(hipMalloc((void**)&b->d_ctl, sizeof(unsigned) * 2));
     if (st == DD_OK) st = hip_status(batch_set_lds(b->lds));
     if (st == DD_OK) {
       hipDeviceProp_t prop;
@@ -170,9 +154,8 @@ dd_status dense_dft_batch_exec(dd_batch_t b, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nk = (int)b->kitems.size();
   if (nk > 0) {
-    hipError_t e = hipMemcpyAsync(b->d_items, b->h_items, sizeof(BatchItem) * nk, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_meta, b->h_meta, sizeof(BatchMeta), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_batch(b->d_items, b->d_meta, b->d_ctl, b->grid1, b->grid2, b->lds, s);
+    const int g2 = b->tab.host->n_second > 0 ? b->grid2 : 0;
+    const hipError_t e = launch_batch(b->tab.host_dev, b->tab.dev, b->tab.cap, b->tab.ctl, b->grid1, g2, b->lds, s);
     if (e != hipSuccess) return hip_status(e);
   }
   for (size_t i = 0; i < b->fb.size(); ++i) {
@@ -192,8 +175,8 @@ dd_status dense_dft_batch_set_buffers(dd_batch_t b, const dd_desc* descs, int32_
   }
   for (int32_t i = 0; i < count; ++i) b->descs[i] = descs[i];
   for (size_t k = 0; k < b->kitems.size(); ++k) {
-    b->h_items[k].x = descs[b->kitems[k]].x;
-    b->h_items[k].X = static_cast<cx<float>*>(descs[b->kitems[k]].X);
+    b->tab.items()[k].x = descs[b->kitems[k]].x;
+    b->tab.items()[k].X = static_cast<cx<float>*>(descs[b->kitems[k]].X);
   }
   return DD_OK;
 }
@@ -212,7 +195,7 @@ dd_status dense_dft_batch_status(dd_batch_t b, uint32_t* flags) {
 dd_status dense_dft_batch_info(dd_batch_t b, int32_t* tasks, int32_t* grid, size_t* scratch_bytes,
                                int32_t* fallback) {
   if (!b) return DD_ERR_INVALID;
-  if (tasks) *tasks = b->h_meta ? b->h_meta->n_first + b->h_meta->n_second : 0;
+  if (tasks) *tasks = b->tab.host ? b->tab.host->n_first + b->tab.host->n_second : 0;
   if (grid) *grid = std::max(b->grid1, b->grid2);
   if (scratch_bytes) *scratch_bytes = b->scratch_bytes;
   if (fallback) *fallback = (int32_t)b->fb.size();

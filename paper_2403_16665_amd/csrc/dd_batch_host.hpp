@@ -13,6 +13,7 @@
 #include "../../include/dense_dft.h"
 #include "dd_batch.hpp"
 #include "dd_host.hpp"
+#include "dd_launch.hpp"
 
 namespace dd {
 
@@ -175,6 +176,39 @@ inline void assign_task_offsets(BatchItem* items, int n, BatchMeta* meta) {
   meta->n_first = t1;
   meta->n_second = t2;
   meta->pad_ = 0;
+}
+
+// Descriptor table of a batch launch: the host view in pinned, coherent
+// (uncached on the device) memory that the staging kernel reads at launch,
+// its device copy, and the two queue heads.
+struct BatchTable {
+  int cap = 0;
+  BatchMeta* host = nullptr;      // host view: meta, then cap items
+  const void* host_dev = nullptr; // the same memory as the device addresses it
+  void* dev = nullptr;
+  unsigned* ctl = nullptr;
+  BatchItem* items() { return batch_table_items(host); }
+};
+
+inline void free_table(BatchTable& t) {
+  if (t.host) (void)hipHostFree(t.host);
+  if (t.dev) (void)hipFree(t.dev);
+  if (t.ctl) (void)hipFree(t.ctl);
+  t = BatchTable{};
+}
+
+inline dd_status alloc_table(BatchTable& t, int cap) {
+  t.cap = cap;
+  const size_t bytes = batch_table_bytes(cap);
+  dd_status st = hip_status(hipHostMalloc((void**)&t.host, bytes, hipHostMallocMapped | hipHostMallocCoherent));
+  void* hd = nullptr;
+  if (st == DD_OK) st = hip_status(hipHostGetDevicePointer(&hd, t.host, 0));
+  t.host_dev = hd;
+  if (st == DD_OK) st = hip_status(hipMalloc(&t.dev, bytes));
+  if (st == DD_OK) st = hip_status(hipMalloc((void**)&t.ctl, sizeof(unsigned) * 2));
+  if (st == DD_OK) std::memset(t.host, 0, bytes);
+  if (st != DD_OK) free_table(t);
+  return st;
 }
 
 }  // namespace dd

@@ -58,12 +58,13 @@ struct BatchItem;
 struct BatchMeta;
 // Persistent batch (dd_batch.hip).  batch_set_lds raises the queue
 // kernel's dynamic-LDS limit to `lds` bytes when needed (call it before
-// launching or capturing launch_batch with that size).  launch_batch: a reset
-// of the two queue heads in ctl, then the two launches of the queue kernel
-// (single-pass and pass-1 tasks, then pass-2 tasks), with counts read from
-// `meta` in device memory.
+// launching or capturing launch_batch with that size).  launch_batch: the
+// staging kernel (copies the descriptor table of `cap` items from its pinned
+// host view `tab_host` to `tab_dev`, clears the two queue heads in ctl), then
+// the queue kernel over the single-pass and pass-1 tasks, then (grid2 > 0)
+// over the pass-2 tasks.
 hipError_t batch_set_lds(size_t lds);
-hipError_t launch_batch(const BatchItem* items, const BatchMeta* meta, unsigned* ctl, int grid1, int grid2,
+hipError_t launch_batch(const void* tab_host, void* tab_dev, int cap, unsigned* ctl, int grid1, int grid2,
                         size_t lds, hipStream_t s);
 int batch_max_blocks_per_cu(size_t lds);
 

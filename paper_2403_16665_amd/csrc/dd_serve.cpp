@@ -60,13 +60,11 @@ struct Slot {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipEvent_t done = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  BatchItem* h_items = nullptr;  // pinned; read by the graph's copy node at replay
-  BatchMeta* h_meta = nullptr;
-  BatchItem* d_items = nullptr;
-  BatchMeta* d_meta = nullptr;
-  unsigned* d_ctl = nullptr;
+  // graphs of the batch launch: [0] one queue launch (no two-pass item),
+  // [1] both; their staging kernel reads `tab` at every replay
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  BatchTable tab;
   std::vector<Req*> reqs;
   bool busy = false;
 };
@@ -178,14 +176,15 @@ bool launch_slot(dd_server* s, Slot& slot, std::unique_lock<std::mutex>& lk) {
       st = class_tables(s, r->d, r->sc, &ct);
       if (st == DD_OK) {
         cx<float>* Y = r->sc.single ? nullptr : reinterpret_cast<cx<float>*>(s->pool + r->scratch_off);
-        fill_item(slot.h_items[i], r->d, *ct, Y);
+        fill_item(slot.tab.items()[i], r->d, *ct, Y);
       }
     }
     // (plain-mode slots have no descriptor table: kreq is empty there)
-    if (st == DD_OK && !kreq.empty()) assign_task_offsets(slot.h_items, (int)kreq.size(), slot.h_meta);
+    if (st == DD_OK && !kreq.empty()) assign_task_offsets(slot.tab.items(), (int)kreq.size(), slot.tab.host);
     const uint64_t t0 = clock_ns();
     for (Req* r : take) r->res.t_start_ns = t0;
-    if (st == DD_OK && !kreq.empty()) st = hip_status(hipGraphLaunch(slot.exec, slot.stream));
+    if (st == DD_OK && !kreq.empty())
+      st = hip_status(hipGraphLaunch(slot.exec[slot.tab.host->n_second > 0 ? 1 : 0], slot.stream));
     for (size_t i = 0; i < freq.size() && st == DD_OK; ++i) {
       Req* r = freq[i];
       dd_plan_t p = nullptr;
@@ -265,15 +264,13 @@ void worker_main(dd_server* s) {
 }
 
 void free_slot(Slot& sl) {
-  if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
-  if (sl.graph) (void)hipGraphDestroy(sl.graph);
+  for (int g = 0; g < 2; ++g) {
+    if (sl.exec[g]) (void)hipGraphExecDestroy(sl.exec[g]);
+    if (sl.graph[g]) (void)hipGraphDestroy(sl.graph[g]);
+  }
   if (sl.done) (void)hipEventDestroy(sl.done);
   if (sl.own_stream && sl.stream) (void)hipStreamDestroy(sl.stream);
-  if (sl.h_items) (void)hipHostFree(sl.h_items);
-  if (sl.h_meta) (void)hipHostFree(sl.h_meta);
-  void* ds[] = {sl.d_items, sl.d_meta, sl.d_ctl};
-  for (void* d : ds)
-    if (d) (void)hipFree(d);
+  free_table(sl.tab);
   sl = Slot{};
 }
 
@@ -306,27 +303,22 @@ dd_status make_slot(dd_server* s, Slot& sl) {
   }
   if (st == DD_OK) st = hip_status(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
   if (plain_mode(s) || st != DD_OK) return st;
-  st = hip_status(hipHostMalloc((void**)&sl.h_items, sizeof(BatchItem) * cap, hipHostMallocDefault));
-  if (st == DD_OK) st = hip_status(hipHostMalloc((void**)&sl.h_meta, sizeof(BatchMeta), hipHostMallocDefault));
-  if (st == DD_OK) st = hip_status(hipMalloc((void**)&sl.d_items, sizeof(BatchItem) * cap));
-  if (st == DD_OK) st = hip_status(hipMalloc((void**)&sl.d_meta, sizeof(BatchMeta)));
-  if (st == DD_OK) st = hip_status(hipMalloc((void**)&sl.d_ctl, sizeof(unsigned) * 2));
+  st = alloc_table(sl.tab, cap);
   if (st != DD_OK) return st;
-  std::memset(sl.h_items, 0, sizeof(BatchItem) * cap);
-  std::memset(sl.h_meta, 0, sizeof(BatchMeta));
-  // a private stream for the capture: the shared caller stream may be in use
+  // a private stream for the captures: the shared caller stream may be in use
   hipStream_t cs = nullptr;
   st = hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   if (st != DD_OK) return st;
-  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    hipError_t e1 = hipMemcpyAsync(sl.d_items, sl.h_items, sizeof(BatchItem) * cap, hipMemcpyHostToDevice, cs);
-    if (e1 == hipSuccess) e1 = hipMemcpyAsync(sl.d_meta, sl.h_meta, sizeof(BatchMeta), hipMemcpyHostToDevice, cs);
-    if (e1 == hipSuccess) e1 = launch_batch(sl.d_items, sl.d_meta, sl.d_ctl, s->grid, s->grid, BATCH_LDS_MAX, cs);
-    e = hipStreamEndCapture(cs, &sl.graph);
+  hipError_t e = hipSuccess;
+  for (int g = 0; g < 2 && e == hipSuccess; ++g) {
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) break;
+    const hipError_t e1 =
+        launch_batch(sl.tab.host_dev, sl.tab.dev, cap, sl.tab.ctl, s->grid, g ? s->grid : 0, BATCH_LDS_MAX, cs);
+    e = hipStreamEndCapture(cs, &sl.graph[g]);
     if (e == hipSuccess) e = e1;
+    if (e == hipSuccess) e = hipGraphInstantiate(&sl.exec[g], sl.graph[g], nullptr, nullptr, 0);
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0);
   (void)hipStreamDestroy(cs);
   return hip_status(e);
 }
@@ -471,6 +463,22 @@ dd_status dense_dft_submit_at(dd_server_t s, const dd_desc* req, uint64_t t_arri
 
 dd_status dense_dft_submit(dd_server_t s, const dd_desc* req, uint64_t* ticket) {
   return dense_dft_submit_at(s, req, clock_ns(), ticket);
+}
+
+dd_status dense_dft_submit_many_at(dd_server_t s, const dd_desc* reqs, const uint64_t* t_arrival_ns, int32_t count,
+                                   uint64_t* tickets, int32_t* submitted) {
+  if (!submitted) return DD_ERR_INVALID;
+  *submitted = 0;
+  if (!s || count < 0 || (count > 0 && (!reqs || !t_arrival_ns || !tickets))) return DD_ERR_INVALID;
+  for (int32_t i = 0; i < count; ++i) {
+    if (i > 0 && t_arrival_ns[i] < t_arrival_ns[i - 1]) return DD_ERR_INVALID;
+    while (clock_ns() < t_arrival_ns[i]) {
+    }
+    const dd_status st = dense_dft_submit_at(s, &reqs[i], t_arrival_ns[i], &tickets[i]);
+    if (st != DD_OK) return st;
+    *submitted = i + 1;
+  }
+  return DD_OK;
 }
 
 dd_status dense_dft_poll(dd_server_t s, uint64_t ticket, dd_result* r) {
