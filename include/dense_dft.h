@@ -128,6 +128,82 @@ dd_status dense_dft_destroy(dd_plan_t plan);
 dd_status dense_dft_plan_info(dd_plan_t plan, int32_t *passes, int64_t *N1,
                               int64_t *N2);
 
+/* ---- Schedules and the tuner ----
+ *
+ * How a plan runs the transform.  One pass: each block holds the whole
+ * alpha*N spectrum of `lines` signals in LDS.  Two passes, N = N1*N2 (the
+ * four-step split of the length-N FFTs of Section 3): pass 1 computes, for
+ * every column n2, the alpha-dense DFT of length N1 (this library's
+ * transform at size N1) times the inter-pass twiddles into a scratch of
+ * alpha*N values; pass 2 computes the length-N2 FFTs of its rows and stores
+ * the bins in natural order.  Zero fields take the planner's rule. */
+typedef struct dd_sched {
+    int32_t passes;   /* 1 or 2 */
+    int32_t lines;    /* one pass: signals per block (0: as many as fit) */
+    int64_t N1, N2;   /* two passes: N = N1*N2 (one pass: N1 = N, N2 = 1) */
+    int32_t jgroup;   /* two passes: values of j per pass-1 block, 1..alpha (0: rule) */
+    int32_t reserved; /* 0 */
+    int64_t chunk;    /* two passes: signals per pass pair (0: 128 MiB of scratch) */
+} dd_sched;
+
+/* As dense_dft_plan, with the schedule given rather than chosen.
+ * Errors: as dense_dft_plan; DD_ERR_UNSUPPORTED if the kernels cannot run N
+ * with this schedule (N1*N2 != N, a length not compiled, LDS too small). */
+dd_status dense_dft_plan_sched(dd_plan_t *out, int64_t N, int32_t alpha, double T,
+                               int64_t batch, dd_dtype dtype, uint32_t flags,
+                               const dd_sched *sched);
+
+/* The schedule a plan runs, every field resolved. */
+dd_status dense_dft_plan_get_sched(dd_plan_t plan, dd_sched *out);
+
+/* The schedules dense_dft_tune measures for this problem class, the
+ * planner's current choice first, every field resolved; up to cap are
+ * written, *count receives their number.  Host only (no device call).
+ * Errors: DD_ERR_INVALID, DD_ERR_UNSUPPORTED (no schedule for N). */
+dd_status dense_dft_sched_candidates(int64_t N, int32_t alpha, int64_t batch, dd_dtype dtype,
+                                     dd_sched *out, int32_t cap, int32_t *count);
+
+typedef struct dd_tune_info {
+    dd_sched best;       /* the fastest schedule measured */
+    float ms_best;       /* its time per execution (per batch for the batch kernel) */
+    float ms_default;    /* the time of the schedule used before the call */
+    int32_t candidates;  /* schedules measured */
+    int32_t reserved;
+} dd_tune_info;
+
+/* Measure, on the current device, every schedule the kernels can run this
+ * problem class with (one pass at each block width; each two-pass split
+ * N1*N2 with each j-group), on temporary buffers of the problem's size, and
+ * record the fastest in the process's tuning table under (N, alpha,
+ * precision of dtype, batch size class floor(log2(batch))).  Later
+ * dense_dft_plan calls of that class use it.  Synchronous.
+ * Errors: as dense_dft_plan, DD_ERR_NOMEM, DD_ERR_DEVICE. */
+dd_status dense_dft_tune(int64_t N, int32_t alpha, int64_t batch, dd_dtype dtype,
+                         dd_tune_info *info);
+
+/* The same for the persistent batch kernel and signals of class (N, alpha):
+ * one pass or each two-pass split of its compiled lengths, timed on a batch
+ * of that class alone (about 2^24 bins).  Later batch plans and servers use
+ * the recorded schedule for the class (a server for classes it has not yet
+ * met).  Errors: DD_ERR_INVALID, DD_ERR_UNSUPPORTED (no batch-kernel
+ * schedule for N), DD_ERR_NOMEM, DD_ERR_DEVICE. */
+dd_status dense_dft_tune_batch(int64_t N, int32_t alpha, dd_tune_info *info);
+
+/* Write the tuning table to a text file / merge one into it (entries of the
+ * file replace those of the same class).  A file named by the environment
+ * variable DD_TUNE_DB is merged at the first use of the table.  Entries are
+ * re-validated when used: one the kernels cannot run falls back to the
+ * planner's rule.  Errors: DD_ERR_INVALID (null path, file not writable /
+ * readable). */
+dd_status dense_dft_tune_save(const char *path);
+dd_status dense_dft_tune_load(const char *path);
+
+/* Empty the tuning table (and skip DD_TUNE_DB from then on). */
+dd_status dense_dft_tune_clear(void);
+
+/* Entries in the tuning table. */
+dd_status dense_dft_tune_entries(int32_t *plans, int32_t *batch_classes);
+
 /* Per-launch timing with HIP events, for benchmarks.  After
  * dense_dft_profile_begin(plan, max_launches), every kernel launch the plan
  * enqueues (up to max_launches) is bracketed by a pair of events recorded on
@@ -177,6 +253,20 @@ typedef struct dd_batch *dd_batch_t;
  * DD_ERR_DEVICE. */
 dd_status dense_dft_batch_plan(dd_batch_t *out, const dd_desc *descs,
                                int32_t count, uint32_t flags);
+
+/* As dense_dft_batch_plan, with every FP32 / complex64 signal run in the
+ * batch kernel with the given schedule (passes, N1, N2; the other fields
+ * are ignored), as the batch tuner does.  Errors: as dense_dft_batch_plan;
+ * DD_ERR_INVALID (null schedule, passes not 1 or 2); DD_ERR_UNSUPPORTED if
+ * the kernel cannot run some FP32 signal with it. */
+dd_status dense_dft_batch_plan_sched(dd_batch_t *out, const dd_desc *descs, int32_t count,
+                                     uint32_t flags, const dd_sched *sched);
+
+/* The schedules the batch kernel can run (N, alpha) with (the candidates of
+ * dense_dft_tune_batch); up to cap written, *count receives their number.
+ * Host only.  Errors: DD_ERR_INVALID, DD_ERR_UNSUPPORTED. */
+dd_status dense_dft_batch_sched_candidates(int64_t N, int32_t alpha, dd_sched *out, int32_t cap,
+                                           int32_t *count);
 
 /* Enqueue the whole batch on `stream`: a staging kernel that reads the
  * descriptor table from pinned host memory into device memory and clears the

@@ -53,6 +53,45 @@ _lib.dense_dft_profile_end.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctyp
 _lib.dense_dft_profile_end.restype = ctypes.c_int
 
 
+class dd_sched(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int32), ("lines", ctypes.c_int32), ("N1", ctypes.c_int64),
+                ("N2", ctypes.c_int64), ("jgroup", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("chunk", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
+class dd_tune_info(ctypes.Structure):
+    _fields_ = [("best", dd_sched), ("ms_best", ctypes.c_float), ("ms_default", ctypes.c_float),
+                ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib.dense_dft_plan_sched.argtypes = [ctypes.POINTER(_vp), _i64, ctypes.c_int32, ctypes.c_double, _i64,
+                                      ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(dd_sched)]
+_lib.dense_dft_plan_sched.restype = ctypes.c_int
+_lib.dense_dft_plan_get_sched.argtypes = [_vp, ctypes.POINTER(dd_sched)]
+_lib.dense_dft_plan_get_sched.restype = ctypes.c_int
+_lib.dense_dft_sched_candidates.argtypes = [_i64, ctypes.c_int32, _i64, ctypes.c_int, ctypes.POINTER(dd_sched),
+                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+_lib.dense_dft_sched_candidates.restype = ctypes.c_int
+_lib.dense_dft_batch_sched_candidates.argtypes = [_i64, ctypes.c_int32, ctypes.POINTER(dd_sched), ctypes.c_int32,
+                                                  ctypes.POINTER(ctypes.c_int32)]
+_lib.dense_dft_batch_sched_candidates.restype = ctypes.c_int
+_lib.dense_dft_tune.argtypes = [_i64, ctypes.c_int32, _i64, ctypes.c_int, ctypes.POINTER(dd_tune_info)]
+_lib.dense_dft_tune.restype = ctypes.c_int
+_lib.dense_dft_tune_batch.argtypes = [_i64, ctypes.c_int32, ctypes.POINTER(dd_tune_info)]
+_lib.dense_dft_tune_batch.restype = ctypes.c_int
+_lib.dense_dft_tune_save.argtypes = [ctypes.c_char_p]
+_lib.dense_dft_tune_save.restype = ctypes.c_int
+_lib.dense_dft_tune_load.argtypes = [ctypes.c_char_p]
+_lib.dense_dft_tune_load.restype = ctypes.c_int
+_lib.dense_dft_tune_clear.argtypes = []
+_lib.dense_dft_tune_clear.restype = ctypes.c_int
+_lib.dense_dft_tune_entries.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+_lib.dense_dft_tune_entries.restype = ctypes.c_int
+
+
 class dd_desc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("alpha", ctypes.c_int32), ("T", ctypes.c_double),
                 ("dtype", ctypes.c_int), ("x", ctypes.c_void_p), ("X", ctypes.c_void_p)]
@@ -61,6 +100,9 @@ class dd_desc(ctypes.Structure):
 _lib.dense_dft_batch_plan.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(dd_desc), ctypes.c_int32,
                                       ctypes.c_uint32]
 _lib.dense_dft_batch_plan.restype = ctypes.c_int
+_lib.dense_dft_batch_plan_sched.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(dd_desc), ctypes.c_int32,
+                                            ctypes.c_uint32, ctypes.POINTER(dd_sched)]
+_lib.dense_dft_batch_plan_sched.restype = ctypes.c_int
 _lib.dense_dft_batch_exec.argtypes = [_vp, _vp]
 _lib.dense_dft_batch_exec.restype = ctypes.c_int
 _lib.dense_dft_batch_set_buffers.argtypes = [_vp, ctypes.POINTER(dd_desc), ctypes.c_int32]
@@ -184,6 +226,79 @@ def dense_dft_destroy(plan: Plan) -> None:
         plan.handle = None
 
 
+# --- schedules and the tuner ---
+def make_sched(passes: int, N1: int = 0, N2: int = 0, jgroup: int = 0, lines: int = 0, chunk: int = 0) -> dd_sched:
+    return dd_sched(int(passes), int(lines), int(N1), int(N2), int(jgroup), 0, int(chunk))
+
+
+def dense_dft_plan_sched(N: int, alpha: int, T: float, batch: int, dtype: int, sched: dd_sched,
+                         flags: int = DD_TWIDDLE_FP64) -> Plan:
+    h = _vp()
+    _check(_lib.dense_dft_plan_sched(ctypes.byref(h), int(N), int(alpha), float(T), int(batch), int(dtype),
+                                     int(flags), ctypes.byref(sched)), "dense_dft_plan_sched")
+    return Plan(h, N, alpha, T, batch, dtype, flags)
+
+
+def dense_dft_plan_get_sched(plan: Plan) -> dict:
+    sc = dd_sched()
+    _check(_lib.dense_dft_plan_get_sched(plan.handle, ctypes.byref(sc)), "dense_dft_plan_get_sched")
+    return sc.as_dict()
+
+
+def dense_dft_sched_candidates(N: int, alpha: int, batch: int, dtype: int) -> list:
+    n = ctypes.c_int32()
+    _check(_lib.dense_dft_sched_candidates(int(N), int(alpha), int(batch), int(dtype), None, 0, ctypes.byref(n)),
+           "dense_dft_sched_candidates")
+    arr = (dd_sched * n.value)()
+    _check(_lib.dense_dft_sched_candidates(int(N), int(alpha), int(batch), int(dtype), arr, n.value,
+                                           ctypes.byref(n)), "dense_dft_sched_candidates")
+    return list(arr)
+
+
+def dense_dft_batch_sched_candidates(N: int, alpha: int) -> list:
+    n = ctypes.c_int32()
+    arr = (dd_sched * 16)()
+    _check(_lib.dense_dft_batch_sched_candidates(int(N), int(alpha), arr, 16, ctypes.byref(n)),
+           "dense_dft_batch_sched_candidates")
+    return list(arr)[:n.value]
+
+
+def _tune_dict(info: dd_tune_info) -> dict:
+    return {"best": info.best.as_dict(), "ms_best": float(info.ms_best), "ms_default": float(info.ms_default),
+            "candidates": int(info.candidates)}
+
+
+def dense_dft_tune(N: int, alpha: int, batch: int, dtype: int) -> dict:
+    info = dd_tune_info()
+    _check(_lib.dense_dft_tune(int(N), int(alpha), int(batch), int(dtype), ctypes.byref(info)), "dense_dft_tune")
+    return _tune_dict(info)
+
+
+def dense_dft_tune_batch(N: int, alpha: int) -> dict:
+    info = dd_tune_info()
+    _check(_lib.dense_dft_tune_batch(int(N), int(alpha), ctypes.byref(info)), "dense_dft_tune_batch")
+    return _tune_dict(info)
+
+
+def dense_dft_tune_save(path: str) -> None:
+    _check(_lib.dense_dft_tune_save(os.fsencode(path)), "dense_dft_tune_save")
+
+
+def dense_dft_tune_load(path: str) -> None:
+    _check(_lib.dense_dft_tune_load(os.fsencode(path)), "dense_dft_tune_load")
+
+
+def dense_dft_tune_clear() -> None:
+    _check(_lib.dense_dft_tune_clear(), "dense_dft_tune_clear")
+
+
+def dense_dft_tune_entries():
+    """(plain-plan entries, batch-kernel class entries) of the tuning table."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.dense_dft_tune_entries(ctypes.byref(a), ctypes.byref(b)), "dense_dft_tune_entries")
+    return int(a.value), int(b.value)
+
+
 # --- many signals of uneven N and alpha in one persistent launch ---
 class Batch:
     """Owning handle of a dd_batch_t."""
@@ -219,6 +334,14 @@ def dense_dft_batch_plan(descs, flags: int = DD_TWIDDLE_FP64) -> Batch:
     arr, n = _desc_array(descs)
     h = _vp()
     _check(_lib.dense_dft_batch_plan(ctypes.byref(h), arr, n, int(flags)), "dense_dft_batch_plan")
+    return Batch(h, n)
+
+
+def dense_dft_batch_plan_sched(descs, sched: dd_sched, flags: int = DD_TWIDDLE_FP64) -> Batch:
+    arr, n = _desc_array(descs)
+    h = _vp()
+    _check(_lib.dense_dft_batch_plan_sched(ctypes.byref(h), arr, n, int(flags), ctypes.byref(sched)),
+           "dense_dft_batch_plan_sched")
     return Batch(h, n)
 
 

@@ -15,6 +15,7 @@
 #include "../../include/dense_dft.h"
 #include "dd_host.hpp"
 #include "dd_launch.hpp"
+#include "dd_tune.hpp"
 
 using namespace dd;
 
@@ -121,6 +122,175 @@ bool factor_two_pass(int64_t N, int rbytes, int64_t* N1, int64_t* N2) {
   return found;
 }
 
+// One-pass blocks hold the spectrum of `lines` signals in LDS within this.
+constexpr size_t SINGLE_BUDGET = 150 * 1024;
+
+// Built-in schedule rules: one pass when the alpha*N spectrum of a signal
+// fits the LDS of one block, else the most balanced two-pass split; tile
+// choices left to configure().
+bool default_sched(int64_t N, int alpha, int rbytes, dd_sched* sc) {
+  *sc = dd_sched{};
+  if (N <= 4096 && len_supported((int)N) && lds_single((int)N, 1, alpha, rbytes) <= SINGLE_BUDGET) {
+    sc->passes = 1;
+    sc->N1 = N;
+    sc->N2 = 1;
+    return true;
+  }
+  int64_t N1 = 0, N2 = 0;
+  if (!factor_two_pass(N, rbytes, &N1, &N2)) return false;
+  sc->passes = 2;
+  sc->N1 = N1;
+  sc->N2 = N2;
+  return true;
+}
+
+// Fill the plan's launch geometry from a schedule (zero fields take the
+// built-in rule); DD_ERR_UNSUPPORTED if the schedule does not fit N, alpha
+// and the compiled kernels.
+dd_status configure(dd_plan* p, const dd_sched& sc) {
+  const int64_t N = p->N, batch = p->batch;
+  const int alpha = p->alpha;
+  const int64_t M = (int64_t)alpha * N;
+  if (sc.passes == 1) {
+    if (N > 4096 || !len_supported((int)N)) return DD_ERR_UNSUPPORTED;
+    const KGeom g = geom_single((int)N, p->rbytes);
+    const size_t per_line = lds_single((int)N, 1, alpha, p->rbytes);
+    if (per_line > SINGLE_BUDGET) return DD_ERR_UNSUPPORTED;
+    int lines = sc.lines;
+    if (lines <= 0) {
+      lines = g.lines;
+      while (lines > 1 && (size_t)lines * per_line > SINGLE_BUDGET) lines /= 2;
+    }
+    if (lines > g.lines || (size_t)lines * per_line > SINGLE_BUDGET) return DD_ERR_UNSUPPORTED;
+    if (lines > batch) lines = (int)batch;
+    p->passes = 1;
+    p->N1 = N;
+    p->N2 = 1;
+    p->s_lines = lines;
+    p->s_TL = g.TL;
+    p->s_lds = lds_single((int)N, lines, alpha, p->rbytes);
+    p->ws_bytes = 0;
+    return DD_OK;
+  }
+  if (sc.passes != 2) return DD_ERR_UNSUPPORTED;
+  const int64_t N1 = sc.N1, N2 = sc.N2;
+  if (N1 < 1 || N2 < 1 || N1 * N2 != N || N1 > 4096 || N2 > 4096) return DD_ERR_UNSUPPORTED;
+  if (!len_supported((int)N1) || !pass2_len_supported((int)N2)) return DD_ERR_UNSUPPORTED;
+  if (sc.jgroup > alpha || sc.jgroup < 0 || sc.chunk < 0) return DD_ERR_UNSUPPORTED;
+  p->passes = 2;
+  p->N1 = N1;
+  p->N2 = N2;
+  const KGeom g1 = geom_pass((int)N1, p->rbytes);
+  const KGeom g2 = geom_pass((int)N2, p->rbytes);
+  p->p1_lines = g1.lines;  // compile-time column count of the kernel
+  p->p1_TL = g1.TL;
+  p->p1_ntile = (int)((N2 + g1.lines - 1) / g1.lines);
+  p->p2_lines = g2.lines;
+  p->p2_TL = g2.TL;
+  p->p2_ntile = (int)((alpha * N1 + g2.lines - 1) / g2.lines);
+  p->p2_lds = lds_pass2((int)N2, g2.lines, p->rbytes);
+  // signals per pass pair: by default the scratch of one chunk within 128 MiB
+  const size_t per_sig = (size_t)M * cx_bytes(p);
+  int64_t chunk = sc.chunk;
+  if (chunk <= 0) chunk = (int64_t)((128u << 20) / per_sig);
+  if (chunk < 1) chunk = 1;
+  if (chunk > batch) chunk = batch;
+  p->chunk = chunk;
+  // j values per pass-1 block: by default all alpha (x and the
+  // post-twiddles are read once per block) unless that leaves fewer than
+  // two blocks per CU
+  int jg = sc.jgroup;
+  if (jg <= 0) {
+    jg = alpha;
+    while (jg > 1 && chunk * p->p1_ntile * ((alpha + jg - 1) / jg) < 512) jg = (jg + 1) / 2;
+  }
+  p->p1_jgroup = jg;
+  p->p1_njg = (alpha + jg - 1) / jg;
+  // stage the block's pre-twiddles in LDS when they take at most 16 KiB
+  const size_t pre_bytes = (size_t)jg * N1 * cx_bytes(p);
+  p->p1_pre_lds = pre_bytes <= 16 * 1024 &&
+                  lds_pass1((int)N1, g1.lines, p->rbytes, jg * (int)N1) <= (size_t)LDS_PASS_MAX ? 1 : 0;
+  p->p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, p->p1_pre_lds ? jg * (int)N1 : 0);
+  p->ws_bytes = (size_t)chunk * per_sig;
+  return DD_OK;
+}
+
+// The tuned schedule of the plan's class if the tuning table has one the
+// kernels can run, else the built-in rules.
+dd_status configure_auto(dd_plan* p) {
+  dd_sched sc;
+  if (tune_lookup_plan(p->N, p->alpha, p->dbl, p->batch, &sc) && configure(p, sc) == DD_OK) return DD_OK;
+  return default_sched(p->N, p->alpha, p->rbytes, &sc) ? configure(p, sc) : DD_ERR_UNSUPPORTED;
+}
+
+// The resolved schedule of a configured plan.
+dd_sched resolved(const dd_plan* p) {
+  dd_sched o{};
+  o.passes = p->passes;
+  o.lines = p->passes == 1 ? p->s_lines : 0;
+  o.N1 = p->N1;
+  o.N2 = p->N2;
+  o.jgroup = p->passes == 2 ? p->p1_jgroup : 0;
+  o.chunk = p->passes == 2 ? p->chunk : 0;
+  return o;
+}
+
+// Plan with the schedule `force`, or (NULL) the tuned schedule of this
+// problem class if the tuning table has one, else the built-in rules.
+dd_status plan_build(dd_plan_t* out, int64_t N, int32_t alpha, double T, int64_t batch, dd_dtype dtype,
+                     uint32_t flags, const dd_sched* force) {
+  if (!out) return DD_ERR_INVALID;
+  *out = nullptr;
+  if (N < 1 || batch < 1 || !(T > 0.0) || !std::isfinite(T)) return DD_ERR_INVALID;
+  if (dtype != DD_F32 && dtype != DD_C64 && dtype != DD_F64 && dtype != DD_C128) return DD_ERR_INVALID;
+  if (flags & ~(uint32_t)(DD_TWIDDLE_FP32 | DD_NO_WORKSPACE)) return DD_ERR_INVALID;
+  if (alpha < 1) return DD_ERR_UNSUPPORTED;
+  const int64_t M = (int64_t)alpha * N;
+  if (M > ((int64_t)1 << 31) || batch > INT64_MAX / M) return DD_ERR_UNSUPPORTED;
+  if (!is_smooth(N)) return DD_ERR_UNSUPPORTED;
+
+  dd_plan* p = new (std::nothrow) dd_plan;
+  if (!p) return DD_ERR_NOMEM;
+  p->N = N;
+  p->alpha = alpha;
+  p->T = T;
+  p->batch = batch;
+  p->dtype = dtype;
+  p->flags = flags;
+  p->dbl = dtype == DD_F64 || dtype == DD_C128;
+  p->rbytes = p->dbl ? 8 : 4;
+  p->in_bytes = dtype == DD_F32 ? 4 : dtype == DD_C128 ? 16 : 8;
+  const bool fp32tw = !p->dbl && (flags & DD_TWIDDLE_FP32);
+  dd_status st = force ? configure(p, *force) : configure_auto(p);
+  if (st != DD_OK) {
+    delete p;
+    return st;
+  }
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return DD_ERR_DEVICE;
+  }
+
+  // Device tables, generated on the GPU (FP64 unless the FP32 variant).
+  hipStream_t s = nullptr;
+  st = gen_stage_table(p, &p->twL1, (int)p->N1, fp32tw, s);
+  if (st == DD_OK) st = gen_table(p, &p->twPre, alpha, p->N1, (int64_t)alpha * p->N1, fp32tw, s);
+  if (st == DD_OK && p->passes == 2) {
+    st = gen_stage_table(p, &p->twL2, (int)p->N2, fp32tw, s);
+    if (st == DD_OK) st = gen_table(p, &p->twQ, alpha, p->N2, M, fp32tw, s);
+    if (st == DD_OK) st = gen_table(p, &p->twPost, p->N1, p->N2, N, fp32tw, s);
+    if (st == DD_OK && !(flags & DD_NO_WORKSPACE)) st = hip_status(hipMalloc(&p->ws, p->ws_bytes));
+  }
+  if (st == DD_OK) st = hip_status(hipStreamSynchronize(s));
+  if (st != DD_OK) {
+    free_tables(p);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return DD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -144,119 +314,77 @@ int32_t dense_dft_version(void) { return 100; }
 
 dd_status dense_dft_plan(dd_plan_t* out, int64_t N, int32_t alpha, double T, int64_t batch, dd_dtype dtype,
                          uint32_t flags) {
-  if (!out) return DD_ERR_INVALID;
-  *out = nullptr;
-  if (N < 1 || batch < 1 || !(T > 0.0) || !std::isfinite(T)) return DD_ERR_INVALID;
-  if (dtype != DD_F32 && dtype != DD_C64 && dtype != DD_F64 && dtype != DD_C128) return DD_ERR_INVALID;
-  if (flags & ~(uint32_t)(DD_TWIDDLE_FP32 | DD_NO_WORKSPACE)) return DD_ERR_INVALID;
-  if (alpha < 1) return DD_ERR_UNSUPPORTED;
-  const int64_t M = (int64_t)alpha * N;
-  if (M > ((int64_t)1 << 31) || batch > INT64_MAX / M) return DD_ERR_UNSUPPORTED;
-  if (!is_smooth(N)) return DD_ERR_UNSUPPORTED;
+  return plan_build(out, N, alpha, T, batch, dtype, flags, nullptr);
+}
 
-  dd_plan* p = new (std::nothrow) dd_plan;
-  if (!p) return DD_ERR_NOMEM;
-  p->N = N;
-  p->alpha = alpha;
-  p->T = T;
-  p->batch = batch;
-  p->dtype = dtype;
-  p->flags = flags;
-  p->dbl = dtype == DD_F64 || dtype == DD_C128;
-  p->rbytes = p->dbl ? 8 : 4;
-  p->in_bytes = dtype == DD_F32 ? 4 : dtype == DD_C128 ? 16 : 8;
-  const bool fp32tw = !p->dbl && (flags & DD_TWIDDLE_FP32);
-  if (hipGetDevice(&p->device) != hipSuccess) {
-    delete p;
-    return DD_ERR_DEVICE;
+dd_status dense_dft_plan_sched(dd_plan_t* out, int64_t N, int32_t alpha, double T, int64_t batch, dd_dtype dtype,
+                               uint32_t flags, const dd_sched* sched) {
+  if (!sched) {
+    if (out) *out = nullptr;
+    return DD_ERR_INVALID;
   }
+  return plan_build(out, N, alpha, T, batch, dtype, flags, sched);
+}
 
-  // Schedule.  One pass when the alpha*N spectrum of a signal fits the LDS
-  // image of one block; otherwise two passes.
-  const size_t single_budget = 150 * 1024;
-  bool single = false;
-  if (N <= 4096 && len_supported((int)N)) {
-    KGeom g = geom_single((int)N, p->rbytes);
-    size_t per_line = lds_single((int)N, 1, alpha, p->rbytes);
-    if (per_line <= single_budget) {
-      single = true;
-      int lines = g.lines;
-      while (lines > 1 && (size_t)lines * per_line > single_budget) lines /= 2;
-      if (lines > batch) lines = (int)batch;
-      p->s_lines = lines < 1 ? 1 : lines;
-      p->s_TL = g.TL;
-      p->s_lds = lds_single((int)N, p->s_lines, alpha, p->rbytes);
-    }
-  }
-  if (single) {
-    p->passes = 1;
-    p->N1 = N;
-    p->N2 = 1;
-  } else {
-    int64_t N1 = 0, N2 = 0;
-    if (!factor_two_pass(N, p->rbytes, &N1, &N2)) {
-      delete p;
-      return DD_ERR_UNSUPPORTED;
-    }
-    p->passes = 2;
-    p->N1 = N1;
-    p->N2 = N2;
-    KGeom g1 = geom_pass((int)N1, p->rbytes);
-    KGeom g2 = geom_pass((int)N2, p->rbytes);
-    p->p1_lines = g1.lines;  // compile-time column count of the kernel
-    p->p1_TL = g1.TL;
-    p->p1_ntile = (int)((N2 + g1.lines - 1) / g1.lines);
-    p->p2_lines = g2.lines;
-    p->p2_TL = g2.TL;
-    p->p2_ntile = (int)((alpha * N1 + g2.lines - 1) / g2.lines);
-    p->p2_lds = lds_pass2((int)N2, g2.lines, p->rbytes);
-    // Signals per pass pair: keep the scratch of one chunk within 128 MiB.
-    const size_t per_sig = (size_t)M * cx_bytes(p);
-    int64_t chunk = (int64_t)((128u << 20) / per_sig);
-    if (chunk < 1) chunk = 1;
-    if (chunk > batch) chunk = batch;
-    if (const char* ev = std::getenv("DD_TUNE_CHUNK")) {
-      long v = std::atol(ev);
-      if (v >= 1) chunk = v < batch ? v : batch;
-    }
-    p->chunk = chunk;
-    // j values per pass-1 block: all alpha (x and the post-twiddles are read
-    // once per block) unless that leaves fewer than two blocks per CU.
-    int jg = alpha;
-    while (jg > 1 && chunk * p->p1_ntile * ((alpha + jg - 1) / jg) < 512) jg = (jg + 1) / 2;
-    if (const char* ev = std::getenv("DD_TUNE_JGROUP")) {
-      long v = std::atol(ev);
-      if (v >= 1 && v <= alpha) jg = (int)v;
-    }
-    p->p1_jgroup = jg;
-    p->p1_njg = (alpha + jg - 1) / jg;
-    // stage the block's pre-twiddles in LDS when they take at most 16 KiB
-    const size_t pre_bytes = (size_t)jg * N1 * cx_bytes(p);
-    p->p1_pre_lds = pre_bytes <= 16 * 1024 &&
-                    lds_pass1((int)N1, g1.lines, p->rbytes, jg * (int)N1) <= (size_t)LDS_PASS_MAX ? 1 : 0;
-    p->p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, p->p1_pre_lds ? jg * (int)N1 : 0);
-    p->ws_bytes = (size_t)chunk * per_sig;
-  }
-
-  // Device tables, generated on the GPU (FP64 unless the FP32 variant).
-  hipStream_t s = nullptr;
-  dd_status st = DD_OK;
-  st = gen_stage_table(p, &p->twL1, (int)p->N1, fp32tw, s);
-  if (st == DD_OK) st = gen_table(p, &p->twPre, alpha, p->N1, (int64_t)alpha * p->N1, fp32tw, s);
-  if (st == DD_OK && p->passes == 2) {
-    st = gen_stage_table(p, &p->twL2, (int)p->N2, fp32tw, s);
-    if (st == DD_OK) st = gen_table(p, &p->twQ, alpha, p->N2, M, fp32tw, s);
-    if (st == DD_OK) st = gen_table(p, &p->twPost, p->N1, p->N2, N, fp32tw, s);
-    if (st == DD_OK && !(flags & DD_NO_WORKSPACE)) st = hip_status(hipMalloc(&p->ws, p->ws_bytes));
-  }
-  if (st == DD_OK) st = hip_status(hipStreamSynchronize(s));
-  if (st != DD_OK) {
-    free_tables(p);
-    delete p;
-    return st;
-  }
-  *out = p;
+dd_status dense_dft_plan_get_sched(dd_plan_t p, dd_sched* out) {
+  if (!p || !out) return DD_ERR_INVALID;
+  *out = resolved(p);
   return DD_OK;
+}
+
+dd_status dense_dft_sched_candidates(int64_t N, int32_t alpha, int64_t batch, dd_dtype dtype, dd_sched* out,
+                                     int32_t cap, int32_t* count) {
+  if (!count || cap < 0 || (cap > 0 && !out)) return DD_ERR_INVALID;
+  *count = 0;
+  if (N < 1 || batch < 1) return DD_ERR_INVALID;
+  if (dtype != DD_F32 && dtype != DD_C64 && dtype != DD_F64 && dtype != DD_C128) return DD_ERR_INVALID;
+  if (alpha < 1) return DD_ERR_UNSUPPORTED;
+  if ((int64_t)alpha * N > ((int64_t)1 << 31) || !is_smooth(N)) return DD_ERR_UNSUPPORTED;
+  // a host-only plan record: configure() validates each schedule
+  dd_plan p;
+  p.N = N;
+  p.alpha = alpha;
+  p.batch = batch;
+  p.dtype = dtype;
+  p.dbl = dtype == DD_F64 || dtype == DD_C128;
+  p.rbytes = p.dbl ? 8 : 4;
+  std::vector<dd_sched> c;
+  auto add = [&](const dd_sched& sc) {
+    if (configure(&p, sc) != DD_OK) return;
+    const dd_sched r = resolved(&p);
+    for (const dd_sched& o : c)
+      if (o.passes == r.passes && o.lines == r.lines && o.N1 == r.N1 && o.N2 == r.N2 && o.jgroup == r.jgroup &&
+          o.chunk == r.chunk)
+        return;
+    c.push_back(r);
+  };
+  if (configure_auto(&p) == DD_OK) add(resolved(&p));
+  if (N <= 4096 && len_supported((int)N)) {
+    for (int lines = geom_single((int)N, p.rbytes).lines; lines >= 1; lines /= 2) {
+      if (lines > batch) continue;
+      dd_sched sc{};
+      sc.passes = 1;
+      sc.lines = lines;
+      sc.N1 = N;
+      sc.N2 = 1;
+      add(sc);
+    }
+  }
+  for (int64_t n2 = 2; n2 <= 4096; n2 *= 2) {
+    if (N % n2) continue;
+    for (int jg = alpha;; jg = (jg + 1) / 2) {
+      dd_sched sc{};
+      sc.passes = 2;
+      sc.N1 = N / n2;
+      sc.N2 = n2;
+      sc.jgroup = jg;
+      add(sc);
+      if (jg == 1) break;
+    }
+  }
+  for (size_t i = 0; i < c.size() && (int32_t)i < cap; ++i) out[i] = c[i];
+  *count = (int32_t)c.size();
+  return c.empty() ? DD_ERR_UNSUPPORTED : DD_OK;
 }
 
 dd_status dense_dft_workspace_size(dd_plan_t p, size_t* bytes) {

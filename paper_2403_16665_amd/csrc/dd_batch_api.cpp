@@ -51,9 +51,8 @@ void batch_free(dd_batch* b) {
 
 }  // namespace
 
-extern "C" {
-
-dd_status dense_dft_batch_plan(dd_batch_t* out, const dd_desc* descs, int32_t count, uint32_t flags) {
+dd_status dd::batch_plan_forced(dd_batch_t* out, const dd_desc* descs, int32_t count, uint32_t flags,
+                                const Sched* force) {
   if (!out) return DD_ERR_INVALID;
   *out = nullptr;
   if (!descs || count < 1) return DD_ERR_INVALID;
@@ -78,7 +77,10 @@ dd_status dense_dft_batch_plan(dd_batch_t* out, const dd_desc* descs, int32_t co
   std::vector<Sched> sched(count);
   for (int32_t i = 0; i < count && st == DD_OK; ++i) {
     const dd_desc& d = descs[i];
-    if (batch_kernel_ok(d, &sched[i])) {
+    const bool kernel = force ? (d.dtype == DD_F32 || d.dtype == DD_C64) && batch_sched_valid(d.N, d.alpha, *force)
+                              : batch_kernel_ok(d, &sched[i]);
+    if (force) sched[i] = *force;
+    if (kernel) {
       b->kitems.push_back(i);
       const auto key = std::make_pair(d.N, (int)d.alpha);
       if (!b->classes.count(key)) {
@@ -147,6 +149,43 @@ dd_status dense_dft_batch_plan(dd_batch_t* out, const dd_desc* descs, int32_t co
   }
   *out = b;
   return DD_OK;
+}
+
+extern "C" {
+
+dd_status dense_dft_batch_plan(dd_batch_t* out, const dd_desc* descs, int32_t count, uint32_t flags) {
+  return batch_plan_forced(out, descs, count, flags, nullptr);
+}
+
+dd_status dense_dft_batch_plan_sched(dd_batch_t* out, const dd_desc* descs, int32_t count, uint32_t flags,
+                                     const dd_sched* sched) {
+  if (out) *out = nullptr;
+  if (!sched || (sched->passes != 1 && sched->passes != 2)) return DD_ERR_INVALID;
+  Sched sc;
+  sc.single = sched->passes == 1;
+  sc.N1 = (int)std::min<int64_t>(sched->N1, 1 << 30);
+  sc.N2 = (int)std::min<int64_t>(sched->passes == 1 ? 1 : sched->N2, 1 << 30);
+  for (int32_t i = 0; descs && i < count; ++i)
+    if ((descs[i].dtype == DD_F32 || descs[i].dtype == DD_C64) && !batch_sched_valid(descs[i].N, descs[i].alpha, sc))
+      return DD_ERR_UNSUPPORTED;
+  return batch_plan_forced(out, descs, count, flags, &sc);
+}
+
+dd_status dense_dft_batch_sched_candidates(int64_t N, int32_t alpha, dd_sched* out, int32_t cap, int32_t* count) {
+  if (!count || cap < 0 || (cap > 0 && !out)) return DD_ERR_INVALID;
+  *count = 0;
+  const dd_status st = batch_check_shape(N, alpha, 1.0, DD_C64);
+  if (st != DD_OK) return st;
+  Sched c[16];
+  const int n = batch_candidates(N, alpha, c, 16);
+  for (int i = 0; i < n && i < cap; ++i) {
+    out[i] = dd_sched{};
+    out[i].passes = c[i].single ? 1 : 2;
+    out[i].N1 = c[i].N1;
+    out[i].N2 = c[i].N2;
+  }
+  *count = n;
+  return n > 0 ? DD_OK : DD_ERR_UNSUPPORTED;
 }
 
 dd_status dense_dft_batch_exec(dd_batch_t b, void* stream) {

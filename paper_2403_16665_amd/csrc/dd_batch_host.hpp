@@ -14,6 +14,7 @@
 #include "dd_batch.hpp"
 #include "dd_host.hpp"
 #include "dd_launch.hpp"
+#include "dd_tune.hpp"
 
 namespace dd {
 
@@ -58,33 +59,69 @@ inline dd_status batch_check_desc(const dd_desc& d) {
   return DD_OK;
 }
 
-// Schedule of one FP32 signal in the batch kernel: one pass when its
-// spectrum fits one block's LDS, else the most balanced N1 x N2 of the
-// compiled pass lengths (N1 <= N2 on ties).  False: not runnable there.
-inline bool batch_schedule(int64_t N, int alpha, Sched* out) {
-  if (N <= 4096 && batch_code(BK_SINGLE, (int)N) >= 0 &&
-      lds_single((int)N, 1, alpha, 4) <= (size_t)BATCH_LDS_MAX) {
-    out->single = true;
-    out->N1 = (int)N;
-    out->N2 = 1;
-    return true;
+// Whether a schedule is runnable in the batch kernel for (N, alpha): one
+// pass of a compiled length whose spectrum fits the block's LDS, or two
+// passes N = N1 * N2 of compiled pass lengths.
+inline bool batch_sched_valid(int64_t N, int alpha, const Sched& sc) {
+  if (sc.single)
+    return N <= 4096 && sc.N1 == N && batch_code(BK_SINGLE, (int)N) >= 0 &&
+           lds_single((int)N, 1, alpha, 4) <= (size_t)BATCH_LDS_MAX;
+  return sc.N1 >= 1 && sc.N2 >= 1 && (int64_t)sc.N1 * sc.N2 == N && batch_code(BK_PASS1, sc.N1) >= 0 &&
+         batch_code(BK_PASS2, sc.N2) >= 0;
+}
+
+// Every schedule the batch kernel can run (N, alpha) with: the tuner's
+// candidates.  Returns their number (at most `cap` written).
+inline int batch_candidates(int64_t N, int alpha, Sched* out, int cap) {
+  int n = 0;
+  Sched one;
+  one.single = true;
+  one.N1 = (int)(N <= 4096 ? N : 0);
+  one.N2 = 1;
+  if (batch_sched_valid(N, alpha, one) && n < cap) out[n++] = one;
+  for (int n2 = 2; n2 <= 4096; n2 *= 2) {
+    if (N % n2 || N / n2 > 4096) continue;
+    Sched two;
+    two.single = false;
+    two.N1 = (int)(N / n2);
+    two.N2 = n2;
+    if (batch_sched_valid(N, alpha, two) && n < cap) out[n++] = two;
   }
+  return n;
+}
+
+// Built-in schedule of one FP32 signal in the batch kernel: one pass when
+// its spectrum fits one block's LDS, else the most balanced N1 x N2 of the
+// compiled pass lengths (N1 <= N2 on ties).  False: not runnable there.
+inline bool batch_default_schedule(int64_t N, int alpha, Sched* out) {
+  Sched c[16];
+  const int n = batch_candidates(N, alpha, c, 16);
   int best = 1 << 30;
-  bool found = false;
-  for (int n2 = 16; n2 <= 512; n2 *= 2) {
-    if (N % n2 || batch_code(BK_PASS2, n2) < 0) continue;
-    const int64_t n1 = N / n2;
-    if (n1 > 512 || batch_code(BK_PASS1, (int)n1) < 0) continue;
-    const int score = std::abs(ilog2(n1) - ilog2(n2)) * 2 + (n1 > n2 ? 1 : 0);
+  for (int i = 0; i < n; ++i) {
+    const int score = c[i].single ? -1 : std::abs(ilog2(c[i].N1) - ilog2(c[i].N2)) * 2 + (c[i].N1 > c[i].N2 ? 1 : 0);
     if (score < best) {
       best = score;
-      out->single = false;
-      out->N1 = (int)n1;
-      out->N2 = n2;
-      found = true;
+      *out = c[i];
     }
   }
-  return found;
+  return n > 0;
+}
+
+// Schedule of (N, alpha) in the batch kernel: the tuned one if the tuning
+// table has a runnable one, else the built-in rule.
+inline bool batch_schedule(int64_t N, int alpha, Sched* out) {
+  dd_sched t;
+  if (tune_lookup_batch(N, alpha, &t)) {
+    Sched sc;
+    sc.single = t.passes == 1;
+    sc.N1 = (int)t.N1;
+    sc.N2 = (int)t.N2;
+    if (batch_sched_valid(N, alpha, sc)) {
+      *out = sc;
+      return true;
+    }
+  }
+  return batch_default_schedule(N, alpha, out);
 }
 
 // Whether a descriptor runs in the batch kernel (FP32 input, compiled lengths).
