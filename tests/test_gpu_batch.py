@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import siggen
-from parity import assert_close, spectrum_rms
+from parity import assert_close, assert_same, spectrum_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -75,8 +75,7 @@ def test_batch_mixed_parity_alone_and_plain(oracle_mod):
     for i in range(0, len(sigs), 5):
         N, a, c, x = sigs[i]
         Xp = dd.alpha_dft(torch.from_numpy(x).cuda(), a, N * 1e-3).cpu().numpy()
-        scale = np.sqrt(np.mean(np.abs(Xp) ** 2))
-        assert np.max(np.abs(Xp - outs[i])) <= 2e-5 * scale
+        assert_same(outs[i], Xp, f"batch vs plain, signal {i}")
 
 
 def test_batch_real_and_complex_same_signal():

@@ -79,8 +79,7 @@ def test_dtypes(oracle_mod, dtype, kind, N, alpha):
         if not np.issubdtype(dtype, np.complexfloating) and M > 1:
             # real input: Hermitian symmetry of the full GPU spectrum
             mirror = X[b][(M - np.arange(M)) % M]
-            scale = np.sqrt(np.mean(np.abs(X[b]) ** 2))
-            assert np.max(np.abs(mirror - np.conj(X[b]))) <= (2e-5 if kind == "f32" else 1e-11) * scale
+            assert_close(mirror, np.conj(X[b]), kind, f"Hermitian symmetry N={N} alpha={alpha}")
 
 
 def test_plain_float64_real_workload(oracle_mod):
