@@ -315,8 +315,11 @@ dd_status dense_dft_exec_many(const dd_desc *descs, int32_t count,
  * A scheduler thread takes queued requests in arrival order whenever a slot
  * is free, as many as the batch size and the memory budget admit, and
  * launches them as one batch while earlier batches still run on the other
- * slots.  A request's footprint is its input and output bytes plus its
- * scratch; the footprints of admitted, unfinished requests never sum past
+ * slots.  Requests above batch_max_bins, the ones the batch kernel is not
+ * built for, and a request alone in its batch (unless
+ * DD_SERVE_DETERMINISTIC) run as plain executions of resident plans, with
+ * the schedules the tuner recorded.  A request's footprint is its input and
+ * output bytes plus its scratch; the footprints of admitted, unfinished requests never sum past
  * hbm_budget_bytes.  Each request is the transform of one dd_desc (the
  * problem of Section 2 for one signal); x and X are the caller's device
  * buffers and must stay allocated and untouched until the request is done.
@@ -329,6 +332,11 @@ typedef struct dd_server *dd_server_t;
 
 #define DD_SERVE_BATCHED 0
 #define DD_SERVE_PLAIN 1
+/* Server flag: every request the batch kernel can run goes through it, even
+ * alone, so that a result does not depend on what else was queued (bit for
+ * bit).  Without it a batch of one runs as a plain execution (lower latency
+ * when the server is idle; the same result within the FP32 tolerance). */
+#define DD_SERVE_DETERMINISTIC 0x100u
 
 typedef struct dd_server_cfg {
     int32_t device;           /* HIP device ordinal */
@@ -338,8 +346,10 @@ typedef struct dd_server_cfg {
     int32_t max_inflight;     /* slots; 0 -> 2 (batched) or 8 (plain); at most 64 */
     int32_t max_batch;        /* requests per batch; 0 -> 256; at most 4096 (plain: 1) */
     int32_t max_queue;        /* queued, not yet admitted requests; 0 -> 65536 */
-    uint32_t flags;           /* DD_TWIDDLE_FP64 or DD_TWIDDLE_FP32 */
+    uint32_t flags;           /* DD_TWIDDLE_FP64 or DD_TWIDDLE_FP32, | DD_SERVE_DETERMINISTIC */
     void *hip_stream;         /* NULL: a stream per slot; else every slot runs on this one */
+    int64_t batch_max_bins;   /* larger requests (alpha*N bins) run as plain executions, which
+                                 fill the device alone; 0 -> 2^20; -1 -> no limit */
 } dd_server_cfg;
 
 typedef struct dd_result {
@@ -368,8 +378,9 @@ typedef struct dd_server_stats {
  * DD_ERR_NOMEM. */
 dd_status dense_dft_server_create(const dd_server_cfg *cfg, dd_server_t *out);
 
-/* Make the tables (or plan) of one request class resident now rather than
- * at its first admission.  Errors as dense_dft_plan, DD_ERR_CLOSED. */
+/* Make the resources of one request class resident now rather than at its
+ * first admission: its batch-kernel tables and the plain plan that serves it
+ * alone or above batch_max_bins.  Errors as dense_dft_plan, DD_ERR_CLOSED. */
 dd_status dense_dft_server_warm(dd_server_t s, int64_t N, int32_t alpha, double T,
                                 dd_dtype dtype);
 

@@ -28,6 +28,7 @@ DD_F32, DD_C64, DD_F64, DD_C128 = 0, 1, 2, 3
 DD_TWIDDLE_FP64, DD_TWIDDLE_FP32 = 0, 1
 DD_NO_WORKSPACE = 2
 DD_SERVE_BATCHED, DD_SERVE_PLAIN = 0, 1
+DD_SERVE_DETERMINISTIC = 0x100
 STATUS = {0: "DD_OK", 1: "DD_ERR_INVALID", 2: "DD_ERR_UNSUPPORTED", 3: "DD_ERR_NOMEM",
           4: "DD_ERR_DEVICE", 5: "DD_ERR_BUSY", 6: "DD_ERR_TOO_LARGE", 7: "DD_ERR_TIMEOUT",
           8: "DD_ERR_CLOSED"}
@@ -390,7 +391,7 @@ def dense_dft_exec_many(descs, stream=None) -> None:
 class dd_server_cfg(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("mode", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
                 ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("max_queue", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p)]
+                ("flags", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p), ("batch_max_bins", ctypes.c_int64)]
 
 
 class dd_result(ctypes.Structure):
@@ -451,9 +452,9 @@ class Server:
 
 def dense_dft_server_create(device: int = 0, mode: int = DD_SERVE_BATCHED, hbm_budget_bytes: int = 0,
                             max_inflight: int = 0, max_batch: int = 0, max_queue: int = 0,
-                            flags: int = DD_TWIDDLE_FP64, hip_stream=None) -> Server:
+                            flags: int = DD_TWIDDLE_FP64, hip_stream=None, batch_max_bins: int = 0) -> Server:
     cfg = dd_server_cfg(int(device), int(mode), int(hbm_budget_bytes), int(max_inflight), int(max_batch),
-                        int(max_queue), int(flags), hip_stream)
+                        int(max_queue), int(flags), hip_stream, int(batch_max_bins))
     h = _vp()
     _check(_lib.dense_dft_server_create(ctypes.byref(cfg), ctypes.byref(h)), "dense_dft_server_create")
     return Server(h, cfg)

@@ -123,7 +123,7 @@ dd_status plain_plan(dd_server* s, const dd_desc& d, dd_plan_t* out) {
   auto it = s->plans.find(key);
   if (it == s->plans.end()) {
     dd_plan_t p = nullptr;
-    const dd_status st = dense_dft_plan(&p, d.N, d.alpha, d.T, 1, d.dtype, s->cfg.flags | DD_NO_WORKSPACE);
+    const dd_status st = dense_dft_plan(&p, d.N, d.alpha, d.T, 1, d.dtype, (s->cfg.flags & DD_TWIDDLE_FP32) | DD_NO_WORKSPACE);
     if (st != DD_OK) return st;
     it = s->plans.emplace(key, p).first;
   }
@@ -162,8 +162,11 @@ bool launch_slot(dd_server* s, Slot& slot, std::unique_lock<std::mutex>& lk) {
   slot.busy = true;
   lk.unlock();
 
+  // a batch of one runs as a plain execution unless results must not
+  // depend on the mix
+  const bool solo_plain = take.size() == 1 && !(s->cfg.flags & DD_SERVE_DETERMINISTIC);
   std::vector<Req*> kreq, freq;
-  for (Req* r : take) (r->kernel ? kreq : freq).push_back(r);
+  for (Req* r : take) (r->kernel && !solo_plain ? kreq : freq).push_back(r);
   std::stable_sort(kreq.begin(), kreq.end(), [](const Req* a, const Req* b) {
     return (int64_t)a->d.alpha * a->d.N > (int64_t)b->d.alpha * b->d.N;
   });
@@ -331,11 +334,13 @@ dd_status classify_shape(const dd_server* s, int64_t N, int alpha, double T, dd_
   r->d.alpha = alpha;
   r->d.T = T;
   r->d.dtype = dtype;
-  r->kernel = !plain_mode(s) && (dtype == DD_F32 || dtype == DD_C64) && batch_schedule(N, alpha, &r->sc);
   const size_t M = (size_t)alpha * N;
-  // two-pass kernel items: one spectrum of FP32 scratch; plain executions:
-  // at most one spectrum of their own precision (none for one pass)
-  r->scratch = r->kernel ? (r->sc.single ? 0 : M * sizeof(cx<float>)) : M * batch_out_elem(dtype);
+  r->kernel = !plain_mode(s) && (dtype == DD_F32 || dtype == DD_C64) &&
+              (s->cfg.batch_max_bins < 0 || (int64_t)M <= s->cfg.batch_max_bins) && batch_schedule(N, alpha, &r->sc);
+  // at most one spectrum of scratch in the request's precision: a two-pass
+  // kernel item's, or a plain execution's (which a kernel request alone in
+  // its batch may become)
+  r->scratch = M * batch_out_elem(dtype);
   r->footprint = (size_t)N * batch_in_elem(dtype) + M * batch_out_elem(dtype) + round_up(r->scratch, POOL_ALIGN);
   return DD_OK;
 }
@@ -354,12 +359,14 @@ dd_status dense_dft_server_create(const dd_server_cfg* cfg, dd_server_t* out) {
   if (c.mode != DD_SERVE_BATCHED && c.mode != DD_SERVE_PLAIN) return DD_ERR_INVALID;
   if (c.max_inflight < 0 || c.max_inflight > 64 || c.max_batch < 0 || c.max_batch > 4096 || c.max_queue < 0)
     return DD_ERR_INVALID;
-  if (c.flags & ~(uint32_t)DD_TWIDDLE_FP32) return DD_ERR_INVALID;
+  if (c.flags & ~(uint32_t)(DD_TWIDDLE_FP32 | DD_SERVE_DETERMINISTIC)) return DD_ERR_INVALID;
+  if (c.batch_max_bins < -1) return DD_ERR_INVALID;
   if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = (size_t)8 << 30;
   if (c.max_inflight == 0) c.max_inflight = c.mode == DD_SERVE_PLAIN ? 8 : 2;
   if (c.max_batch == 0) c.max_batch = 256;
   if (c.mode == DD_SERVE_PLAIN) c.max_batch = 1;
   if (c.max_queue == 0) c.max_queue = 65536;
+  if (c.batch_max_bins == 0) c.batch_max_bins = (int64_t)1 << 20;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || c.device < 0 || c.device >= ndev) return DD_ERR_DEVICE;
 
@@ -418,10 +425,12 @@ dd_status dense_dft_server_warm(dd_server_t s, int64_t N, int32_t alpha, double 
   (void)hipSetDevice(s->cfg.device);
   {
     std::lock_guard<std::mutex> rg(s->mu_res);
+    // both paths may serve the class: batch-kernel tables and a plain plan
     if (r.kernel) {
       const ClassTables* ct = nullptr;
       st = class_tables(s, r.d, r.sc, &ct);
-    } else {
+    }
+    if (st == DD_OK && (!r.kernel || !(s->cfg.flags & DD_SERVE_DETERMINISTIC))) {
       dd_plan_t p = nullptr;
       st = plain_plan(s, r.d, &p);
     }

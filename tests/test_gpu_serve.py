@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import siggen
-from parity import assert_close, spectrum_rms
+from parity import assert_close, assert_same, spectrum_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -59,7 +59,8 @@ def test_serve_mix_parity_alone_and_plain(oracle_mod):
     reqs = make_requests(31, 40, extra=[(24, 4), (3 * 2 ** 14, 3)])
     reqs.append((1024, 4, dd.DD_F64, siggen.tones_real(np.random.default_rng(8), 1024, 1e-3, 4)[0]))
     xs, Xs = device_buffers(reqs)
-    srv = dd.dense_dft_server_create(hbm_budget_bytes=1 << 30, max_inflight=2, max_batch=8)
+    srv = dd.dense_dft_server_create(hbm_budget_bytes=1 << 30, max_inflight=2, max_batch=8,
+                                     flags=dd.DD_SERVE_DETERMINISTIC, batch_max_bins=-1)
     dd.dense_dft_server_pause(srv, True)      # queue everything, then let the batches form
     tickets = [dd.dense_dft_submit(srv, (N, a, N * 1e-3, c, xs[i], Xs[i])) for i, (N, a, c, _) in enumerate(reqs)]
     assert dd.dense_dft_poll(srv, tickets[0]) is None
@@ -93,7 +94,39 @@ def test_serve_mix_parity_alone_and_plain(oracle_mod):
         if c == dd.DD_F64:
             continue
         Xp = dd.alpha_dft(xs[i], a, N * 1e-3).cpu().numpy()
-        assert np.max(np.abs(Xp - mixed[i])) <= 2e-5 * np.sqrt(np.mean(np.abs(Xp) ** 2))
+        assert_same(mixed[i], Xp, f"served vs plain, request {i}")
+    dd.dense_dft_server_destroy(srv)
+
+
+def test_serve_default_routing_alone_and_in_mix(oracle_mod):
+    """Default server: a request alone runs as a plain execution, large ones
+    always do, the rest batch; each result is the same alone and in the mix
+    within the FP32 bound, and matches the oracle."""
+    import torch
+    import paper_2403_16665_amd as dd
+    reqs = make_requests(34, 24, nmax=262144, extra=[(262144, 16), (131072, 8)])
+    xs, Xs = device_buffers(reqs)
+    srv = dd.dense_dft_server_create(hbm_budget_bytes=2 << 30, max_batch=32)
+    dd.dense_dft_server_pause(srv, True)
+    tickets = [dd.dense_dft_submit(srv, (N, a, N * 1e-3, c, xs[i], Xs[i])) for i, (N, a, c, _) in enumerate(reqs)]
+    dd.dense_dft_server_pause(srv, False)
+    res = [dd.dense_dft_wait(srv, t, 30_000_000) for t in tickets]
+    assert all(r["status"] == 0 for r in res)
+    st = dd.dense_dft_server_stats(srv)
+    big = sum(1 for N, a, _, _ in reqs if a * N > (1 << 20))
+    assert big >= 1 and st["fallback_requests"] >= big and st["kernel_requests"] >= 1
+    mixed = [X.cpu().numpy() for X in Xs]
+    rng = np.random.default_rng(9)
+    for i, (N, a, c, x) in enumerate(reqs):
+        X2 = torch.zeros_like(Xs[i])
+        torch.cuda.synchronize()
+        r = dd.dense_dft_wait(srv, dd.dense_dft_submit(srv, (N, a, N * 1e-3, c, xs[i], X2)), 30_000_000)
+        assert r["status"] == 0 and r["batch_requests"] == 1
+        assert_same(mixed[i], X2.cpu().numpy(), f"request {i} in the mix vs alone")
+        if i % 3 == 0:
+            bins = siggen.bin_subset(rng, a * N, 128)
+            assert_close(mixed[i][bins], oracle_mod.alpha_dft_bins(x, a, N * 1e-3, bins), "f32",
+                         f"routed N={N} alpha={a}", full_rms=spectrum_rms(x, N * 1e-3))
     dd.dense_dft_server_destroy(srv)
 
 
@@ -186,6 +219,4 @@ def test_serve_batches_overlap_under_load():
     ref = [dd.alpha_dft(x, a, N * 1e-3) for x in xs]
     torch.cuda.synchronize()
     for i in range(0, count, 7):
-        R = ref[i % 4]
-        err = (Xs[i] - R).abs().max().item()
-        assert err <= 2e-5 * R.abs().pow(2).mean().sqrt().item(), f"request {i}: {err}"
+        assert_same(Xs[i].cpu().numpy(), ref[i % 4].cpu().numpy(), f"request {i}")
