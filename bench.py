@@ -186,7 +186,7 @@ def run_uneven(args):
                    "N_range": [min(n for n, _ in mix), max(n for n, _ in mix)],
                    "alphas": sorted(set(a for _, a in mix)), "input": "complex64", "dt": dt},
         "batch": {"tasks": tasks, "grid": grid, "scratch_bytes": scratch, "fallback_signals": fb,
-                  "launches_per_step": "1 reset + 2 queue kernels"},
+                  "launches_per_step": "1 staging kernel + 1 or 2 queue kernels"},
         "plain": {"value": bins / (ms_p * 1e-3), "ms_per_step": ms_p, "wall_ms_per_step": wall_p,
                   "launches_per_step": "1000 execs"},
         "batched_over_plain": ms_p / ms_b,
