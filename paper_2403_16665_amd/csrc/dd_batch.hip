@@ -52,9 +52,10 @@ __device__ __forceinline__ void run_single(const BatchItem* __restrict__ items, 
                                            int tid) {
   const BatchItem& it = items[item];
   DenseArgs<float> a = item_args(it);
-  a.lines = it.lines1;
+  a.lines = 1;
   a.twL = it.twL1;
-  body_single<float, AnyIn<float>, L>(AnyIn<float>{it.x, it.real}, it.X, a, sub, BATCH_THREADS, smem, tid);
+  body_single_groups<float, AnyIn<float>, L>(AnyIn<float>{it.x, it.real}, it.X, a, sub, it.lines1, BATCH_THREADS,
+                                             smem, tid);
 }
 
 template <int L>
@@ -79,17 +80,18 @@ __device__ __forceinline__ void run_pass2(const BatchItem* __restrict__ items, i
   body_pass2<float, L, batch_lines(L)>(it.Y, it.X, a, sub, smem, tid);
 }
 
-// Persistent queue over the tasks of launch `which` (0: single-pass and
-// pass-1 tasks, 1: pass-2 tasks): every block takes the next task until the
+// Persistent queue over the tasks of one launch (WHICH = 0: single-pass and
+// pass-1 tasks; 1: pass-2 tasks): every block takes the next task until the
 // queue is empty.  No task of a launch depends on another task of the same
-// launch, so no block ever waits for another.
-__global__ __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_batch(
-    const BatchItem* __restrict__ items, const BatchMeta* __restrict__ meta, int which,
-    unsigned* __restrict__ head) {
-  extern __shared__ __align__(16) unsigned char smem[];
+// launch, so no block ever waits for another.  The pass-2 kernel holds only
+// the light pass-2 paths, so it runs at the occupancy those allow; the first
+// kernel holds the heavy paths and is held to two waves per SIMD (256 VGPRs).
+template <int WHICH>
+__device__ __forceinline__ void batch_loop(const BatchItem* __restrict__ items, const BatchMeta* __restrict__ meta,
+                                           unsigned* __restrict__ head, unsigned char* smem) {
   __shared__ int s_task;
   const int nitems = meta->nitems;
-  const int count = which ? meta->n_second : meta->n_first;
+  const int count = WHICH ? meta->n_second : meta->n_first;
   if (nitems <= 0) return;
   for (;;) {
     if (threadIdx.x == 0) s_task = (int)atomicAdd(head, 1u);
@@ -103,53 +105,78 @@ __global__ __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(2
     int lo = 0, hi = nitems - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      const int tm = which ? items[mid].t2 : items[mid].t1;
+      const int tm = WHICH ? items[mid].t2 : items[mid].t1;
       if (tm <= ti) lo = mid;
       else hi = mid - 1;
     }
     const int k = lo;
-    const int sub = ti - (which ? items[k].t2 : items[k].t1);
-    const int code = which ? items[k].code2 : items[k].code1;
+    const int sub = ti - (WHICH ? items[k].t2 : items[k].t1);
+    const int code = WHICH ? items[k].code2 : items[k].code1;
     // The thread index passes through an opaque move every iteration, so that
     // no code path's thread-dependent address arithmetic is hoisted out of
     // the task loop (hoisted, the invariants of all paths stay live at once).
     int tid;
     asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
-    switch (code) {
+    if (WHICH == 0) {
+      switch (code) {
 #define DD_S(LL)                                  \
   case batch_code(BK_SINGLE, LL):                 \
     run_single<LL>(items, k, sub, smem, tid);     \
     break;
-      DD_BATCH_SINGLE(DD_S)
+        DD_BATCH_SINGLE(DD_S)
 #undef DD_S
 #define DD_P1(LL)                                 \
   case batch_code(BK_PASS1, LL):                  \
     run_pass1<LL>(items, k, sub, smem, tid);      \
     break;
-      DD_BATCH_P1(DD_P1)
+        DD_BATCH_P1(DD_P1)
 #undef DD_P1
+        default:
+          break;
+      }
+    } else {
+      switch (code) {
 #define DD_P2(LL)                                 \
   case batch_code(BK_PASS2, LL):                  \
     run_pass2<LL>(items, k, sub, smem, tid);      \
     break;
-      DD_BATCH_P2(DD_P2)
+        DD_BATCH_P2(DD_P2)
 #undef DD_P2
-      default:
-        break;
+        default:
+          break;
+      }
     }
   }
 }
 
-hipError_t batch_set_lds(size_t lds) {
-  // dynamic LDS plus the kernel's static word beyond the default 64 KiB
+__global__ __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_first(
+    const BatchItem* __restrict__ items, const BatchMeta* __restrict__ meta, unsigned* __restrict__ head) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  batch_loop<0>(items, meta, head, smem);
+}
+
+__global__ __launch_bounds__(BATCH_THREADS) void k_batch_second(const BatchItem* __restrict__ items,
+                                                                const BatchMeta* __restrict__ meta,
+                                                                unsigned* __restrict__ head) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  batch_loop<1>(items, meta, head, smem);
+}
+
+hipError_t batch_set_lds(size_t lds1, size_t lds2) {
+  // dynamic LDS plus the kernels' static word beyond the default 64 KiB
   // needs the attribute; it is set outside any stream capture
-  if (lds + 64 <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+  hipError_t e = hipSuccess;
+  if (lds1 + 64 > 64 * 1024)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_first), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds1);
+  if (e == hipSuccess && lds2 + 64 > 64 * 1024)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_second),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+  return e;
 }
 
 hipError_t launch_batch(const void* tab_host, void* tab_dev, int cap, unsigned* ctl, int grid1, int grid2,
-                        size_t lds, hipStream_t s) {
+                        size_t lds1, size_t lds2, hipStream_t s) {
   const int words = (int)(batch_table_bytes(cap) / 16);
   const int gstage = (words + 1023) / 1024;
   hipLaunchKernelGGL(k_batch_stage, dim3(gstage), dim3(256), 0, s, static_cast<const uint4*>(tab_host),
@@ -158,16 +185,19 @@ hipError_t launch_batch(const void* tab_host, void* tab_dev, int cap, unsigned* 
   if (e != hipSuccess) return e;
   const BatchMeta* meta = static_cast<const BatchMeta*>(tab_dev);
   const BatchItem* items = batch_table_items(meta);
-  hipLaunchKernelGGL(k_batch, dim3(grid1), dim3(BATCH_THREADS), lds, s, items, meta, 0, ctl);
+  hipLaunchKernelGGL(k_batch_first, dim3(grid1), dim3(BATCH_THREADS), lds1, s, items, meta, ctl);
   e = hipGetLastError();
   if (e != hipSuccess || grid2 <= 0) return e;
-  hipLaunchKernelGGL(k_batch, dim3(grid2), dim3(BATCH_THREADS), lds, s, items, meta, 1, ctl + 1);
+  hipLaunchKernelGGL(k_batch_second, dim3(grid2), dim3(BATCH_THREADS), lds2, s, items, meta, ctl + 1);
   return hipGetLastError();
 }
 
-int batch_max_blocks_per_cu(size_t lds) {
+int batch_max_blocks_per_cu(int which, size_t lds) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch, BATCH_THREADS, lds) != hipSuccess) return 1;
+  const hipError_t e =
+      which ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_second, BATCH_THREADS, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_first, BATCH_THREADS, lds);
+  if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 

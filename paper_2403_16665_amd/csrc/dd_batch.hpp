@@ -16,7 +16,9 @@
 namespace dd {
 
 constexpr int BATCH_THREADS = 256;
-constexpr int BATCH_LDS_MAX = 64 * 1024;
+// The first queue kernel holds two blocks per CU (its register use), so a
+// block may take up to half of the CU's 160 KiB of LDS.
+constexpr int BATCH_LDS_MAX = 80 * 1024;
 
 // Lengths compiled into the batch kernel, per kind.
 #define DD_BATCH_SINGLE(X) \
@@ -45,6 +47,39 @@ __host__ __device__ constexpr int batch_code(int kind, int L) {
 
 // Lines per 256-thread block for a pass kernel of length L.
 __host__ __device__ constexpr int batch_lines(int L) { return BATCH_THREADS / line_threads(L); }
+// Thread groups sharing one single-pass signal of length L (each takes its
+// own values of j): as many as the block holds, but no more than alpha needs
+// (rounded up to a power of two) and no more than the LDS holds; 0 if not
+// even one fits.  A switch over the compiled lengths: the layout's row
+// stride is a compile-time constant.
+__host__ __device__ inline int batch_single_groups(int L, int alpha) {
+  switch (L) {
+#define DD_SG(LL)                                                                                        \
+  case LL: {                                                                                             \
+    int g = BATCH_THREADS / line_threads(LL);                                                            \
+    while (g > 1 && (g / 2 >= alpha || (size_t)single_groups_lds_elems<LL>(g, alpha) * 8 > (size_t)BATCH_LDS_MAX)) \
+      g /= 2;                                                                                            \
+    return (size_t)single_groups_lds_elems<LL>(g, alpha) * 8 <= (size_t)BATCH_LDS_MAX ? g : 0;          \
+  }
+    DD_BATCH_SINGLE(DD_SG)
+#undef DD_SG
+    default:
+      return 0;
+  }
+}
+
+// LDS bytes of a single-pass task of length L with `groups` thread groups.
+__host__ __device__ inline size_t batch_single_lds(int L, int alpha, int groups) {
+  switch (L) {
+#define DD_SL(LL) \
+  case LL:        \
+    return (size_t)single_groups_lds_elems<LL>(groups, alpha) * 8;
+    DD_BATCH_SINGLE(DD_SL)
+#undef DD_SL
+    default:
+      return (size_t)-1;
+  }
+}
 
 // Device descriptor of one signal of a batch (FP32 arithmetic; real float or
 // complex float input).
@@ -59,7 +94,7 @@ struct BatchItem {
   const cx<float>* twL2;  // stage twiddles of the N2 line
   int64_t N;
   int N1, N2, alpha, real;
-  int lines1, ntile1, jgroup, njg, pre_lds;  // one pass: lines1 = signals per block (1)
+  int lines1, ntile1, jgroup, njg, pre_lds;  // one pass: lines1 = thread groups sharing the signal
   int ntile2;
   int p1_tasks;           // pass-1 tasks of the item
   int code1, code2;       // code paths: single or pass 1; pass 2 (-1: one pass)

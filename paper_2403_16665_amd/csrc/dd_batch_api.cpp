@@ -32,7 +32,7 @@ struct dd_batch {
   BatchTable tab;                          // descriptor table (queue order)
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
-  size_t lds = 0;
+  size_t lds1 = 0, lds2 = 0;
   int grid1 = 1, grid2 = 1;
 };
 
@@ -116,7 +116,8 @@ dd_status dd::batch_plan_forced(dd_batch_t* out, const dd_desc* descs, int32_t c
       const dd_desc& d = descs[b->kitems[k]];
       const ClassTables& ct = b->classes[std::make_pair(d.N, (int)d.alpha)];
       fill_item(items[k], d, ct, ysoff[k] >= 0 ? static_cast<cx<float>*>(b->scratch) + ysoff[k] : nullptr);
-      b->lds = std::max(b->lds, item_lds(items[k]));
+      b->lds1 = std::max(b->lds1, item_lds1(items[k]));
+      b->lds2 = std::max(b->lds2, item_lds2(items[k]));
     }
     BatchMeta meta;
     assign_task_offsets(items.data(), nk, &meta);
@@ -125,13 +126,13 @@ dd_status dd::batch_plan_forced(dd_batch_t* out, const dd_desc* descs, int32_t c
       std::memcpy(b->tab.items(), items.data(), sizeof(BatchItem) * nk);
       *b->tab.host = meta;
     }
-    if (st == DD_OK) st = hip_status(batch_set_lds(b->lds));
+    if (st == DD_OK) st = hip_status(batch_set_lds(b->lds1, b->lds2));
     if (st == DD_OK) {
       hipDeviceProp_t prop;
       st = hip_status(hipGetDeviceProperties(&prop, b->device));
-      const int grid = prop.multiProcessorCount * batch_max_blocks_per_cu(b->lds);
-      b->grid1 = std::max(1, std::min(grid, meta.n_first));
-      b->grid2 = std::max(1, std::min(grid, meta.n_second));
+      const int cus = prop.multiProcessorCount;
+      b->grid1 = std::max(1, std::min(cus * batch_max_blocks_per_cu(0, b->lds1), meta.n_first));
+      b->grid2 = std::max(1, std::min(cus * batch_max_blocks_per_cu(1, b->lds2), meta.n_second));
     }
   }
   // fallback signals: plain plans of one signal each
@@ -194,7 +195,8 @@ dd_status dense_dft_batch_exec(dd_batch_t b, void* stream) {
   const int nk = (int)b->kitems.size();
   if (nk > 0) {
     const int g2 = b->tab.host->n_second > 0 ? b->grid2 : 0;
-    const hipError_t e = launch_batch(b->tab.host_dev, b->tab.dev, b->tab.cap, b->tab.ctl, b->grid1, g2, b->lds, s);
+    const hipError_t e =
+        launch_batch(b->tab.host_dev, b->tab.dev, b->tab.cap, b->tab.ctl, b->grid1, g2, b->lds1, b->lds2, s);
     if (e != hipSuccess) return hip_status(e);
   }
   for (size_t i = 0; i < b->fb.size(); ++i) {

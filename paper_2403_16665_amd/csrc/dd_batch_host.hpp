@@ -64,8 +64,7 @@ inline dd_status batch_check_desc(const dd_desc& d) {
 // passes N = N1 * N2 of compiled pass lengths.
 inline bool batch_sched_valid(int64_t N, int alpha, const Sched& sc) {
   if (sc.single)
-    return N <= 4096 && sc.N1 == N && batch_code(BK_SINGLE, (int)N) >= 0 &&
-           lds_single((int)N, 1, alpha, 4) <= (size_t)BATCH_LDS_MAX;
+    return N <= 4096 && sc.N1 == N && batch_code(BK_SINGLE, (int)N) >= 0 && batch_single_groups((int)N, alpha) > 0;
   return sc.N1 >= 1 && sc.N2 >= 1 && (int64_t)sc.N1 * sc.N2 == N && batch_code(BK_PASS1, sc.N1) >= 0 &&
          batch_code(BK_PASS2, sc.N2) >= 0;
 }
@@ -175,7 +174,7 @@ inline void fill_item(BatchItem& it, const dd_desc& d, const ClassTables& ct, cx
   it.real = d.dtype == DD_F32 ? 1 : 0;
   it.scale = (float)(d.T / (double)d.N);
   if (sc.single) {
-    it.lines1 = 1;
+    it.lines1 = batch_single_groups(sc.N1, d.alpha);
     it.p1_tasks = 1;
     it.code1 = batch_code(BK_SINGLE, sc.N1);
     it.code2 = -1;
@@ -193,11 +192,21 @@ inline void fill_item(BatchItem& it, const dd_desc& d, const ClassTables& ct, cx
   }
 }
 
-// LDS bytes the item's tasks need.
-inline size_t item_lds(const BatchItem& it) {
-  if (it.code2 < 0) return lds_single(it.N1, 1, it.alpha, 4);
-  const size_t p1 = (size_t)pass1_lds_elems(it.N1, batch_lines(it.N1), it.pre_lds ? it.alpha * it.N1 : 0) * 8;
-  return std::max(p1, lds_pass2(it.N2, batch_lines(it.N2), 4));
+// LDS bytes the item's tasks need in the first (single-pass / pass-1) and
+// the second (pass-2) queue kernel.
+inline size_t item_lds1(const BatchItem& it) {
+  if (it.code2 < 0) return batch_single_lds(it.N1, it.alpha, it.lines1);
+  return (size_t)pass1_lds_elems(it.N1, batch_lines(it.N1), it.pre_lds ? it.alpha * it.N1 : 0) * 8;
+}
+inline size_t item_lds2(const BatchItem& it) { return it.code2 < 0 ? 0 : lds_pass2(it.N2, batch_lines(it.N2), 4); }
+
+// Largest pass-2 LDS of any compiled pass-2 length (a server's fixed launch).
+inline size_t batch_lds2_max() {
+  size_t m = 0;
+#define DD_L2(LL) m = std::max(m, lds_pass2(LL, batch_lines(LL), 4));
+  DD_BATCH_P2(DD_L2)
+#undef DD_L2
+  return m;
 }
 
 // Task offsets of items already in queue order; fills the counts of meta.

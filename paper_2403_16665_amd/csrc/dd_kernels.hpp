@@ -163,6 +163,57 @@ __device__ __forceinline__ void body_single(const InAcc& x, cx<R>* __restrict__ 
   __syncthreads();  // the image is reused by the next task of a persistent block
 }
 
+// One pass, one signal per block, `groups` groups of TL threads: group g
+// takes the values j = g, g + groups, ... (the batch kernel's blocks have a
+// fixed width, so the alpha pre-twiddled FFTs of one signal share it rather
+// than leaving all but TL threads idle).  Threads beyond the groups take part
+// in the barriers only.  LDS: one exchange row per group, then the alpha*L
+// spectrum image, stored contiguously at the end.
+template <int L>
+__host__ __device__ constexpr int single_groups_lds_elems(int groups, int alpha) {
+  return RowLayout<L>::elems(groups) + alpha * L;
+}
+
+template <typename R, class InAcc, int L>
+__device__ __forceinline__ void body_single_groups(const InAcc& x, cx<R>* __restrict__ X, const DenseArgs<R>& a,
+                                                   int64_t sig, int groups, int nt, unsigned char* smem, int tid) {
+  constexpr LinePlan P = make_line_plan(L);
+  constexpr int EPT = P.EPT;
+  constexpr int TL = L / EPT;
+  cx<R>* ex = reinterpret_cast<cx<R>*>(smem);
+  cx<R>* img = ex + RowLayout<L>::elems(groups);
+  const int t = tid % TL, g = tid / TL;
+  const bool member = g < groups;
+  const int M1 = a.alpha * L;
+  cx<R> xv[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e)
+    xv[e] = member ? cscale(x(sig * a.x_stride, (unsigned)(t + TL * e)), a.scale) : cx<R>{(R)0, (R)0};
+  const RowLayout<L> lay(member ? g : 0);
+  for (int j0 = 0; j0 < a.alpha; j0 += groups) {  // uniform over the block
+    const int j = j0 + g;
+    const bool act = member && j < a.alpha;
+    cx<R> v[EPT];
+    if (j == 0 || !act) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[e] = xv[e];
+    } else {
+      const cx<R>* __restrict__ pre = a.twPre + j * L + t;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pre[TL * e]);
+    }
+    line_fft<R, L, (TL <= 64)>(v, t, ex, lay, a.twL, act);
+    if (act) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) img[a.alpha * (t + TL * e) + j] = v[e];
+    }
+  }
+  __syncthreads();
+  cx<R>* dst = X + sig * a.y_stride;  // y_stride == alpha * L
+  for (int i = tid; i < M1; i += nt) dst[i] = img[i];
+  __syncthreads();  // the image is reused by the next task of a persistent block
+}
+
 // Pass 1: block = (signal, tile of C columns n2, group of j values).  Thread
 // (c, t) with c fastest owns column n2 = tile*C + c, samples n1 = t + TL e.
 // Output Y[alpha k1 + j][n2] times the inter-pass twiddle

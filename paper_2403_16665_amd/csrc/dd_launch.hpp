@@ -56,17 +56,18 @@ DD_DECL_LAUNCHERS(double)
 
 struct BatchItem;
 struct BatchMeta;
-// Persistent batch (dd_batch.hip).  batch_set_lds raises the queue
-// kernel's dynamic-LDS limit to `lds` bytes when needed (call it before
-// launching or capturing launch_batch with that size).  launch_batch: the
-// staging kernel (copies the descriptor table of `cap` items from its pinned
-// host view `tab_host` to `tab_dev`, clears the two queue heads in ctl), then
-// the queue kernel over the single-pass and pass-1 tasks, then (grid2 > 0)
-// over the pass-2 tasks.
-hipError_t batch_set_lds(size_t lds);
+// Persistent batch (dd_batch.hip).  batch_set_lds raises the two queue
+// kernels' dynamic-LDS limits to lds1 / lds2 bytes when needed (call it
+// before launching or capturing launch_batch with those sizes).
+// launch_batch: the staging kernel (copies the descriptor table of `cap`
+// items from its pinned host view `tab_host` to `tab_dev`, clears the two
+// queue heads in ctl), then the first queue kernel over the single-pass and
+// pass-1 tasks, then (grid2 > 0) the second over the pass-2 tasks.
+// batch_max_blocks_per_cu: occupancy of queue kernel `which` (0, 1).
+hipError_t batch_set_lds(size_t lds1, size_t lds2);
 hipError_t launch_batch(const void* tab_host, void* tab_dev, int cap, unsigned* ctl, int grid1, int grid2,
-                        size_t lds, hipStream_t s);
-int batch_max_blocks_per_cu(size_t lds);
+                        size_t lds1, size_t lds2, hipStream_t s);
+int batch_max_blocks_per_cu(int which, size_t lds);
 
 // LDS bytes of each kernel for a given length and lines per block.
 inline size_t lds_single(int L, int lines, int alpha, int rbytes) {

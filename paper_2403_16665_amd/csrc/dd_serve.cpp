@@ -75,7 +75,7 @@ using PlanKey = std::tuple<int64_t, int, uint64_t, int>;  // N, alpha, bits of T
 
 struct dd_server {
   dd_server_cfg cfg{};
-  int grid = 1;
+  int grid1 = 1, grid2 = 1;
   std::thread worker;
   std::mutex mu;  // queue, tickets, budget, pool ranges, slots' request lists, stats
   std::condition_variable cv_work, cv_done;
@@ -317,7 +317,8 @@ dd_status make_slot(dd_server* s, Slot& sl) {
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) break;
     const hipError_t e1 =
-        launch_batch(sl.tab.host_dev, sl.tab.dev, cap, sl.tab.ctl, s->grid, g ? s->grid : 0, BATCH_LDS_MAX, cs);
+        launch_batch(sl.tab.host_dev, sl.tab.dev, cap, sl.tab.ctl, s->grid1, g ? s->grid2 : 0, BATCH_LDS_MAX,
+                     batch_lds2_max(), cs);
     e = hipStreamEndCapture(cs, &sl.graph[g]);
     if (e == hipSuccess) e = e1;
     if (e == hipSuccess) e = hipGraphInstantiate(&sl.exec[g], sl.graph[g], nullptr, nullptr, 0);
@@ -384,11 +385,14 @@ dd_status dense_dft_server_create(const dd_server_cfg* cfg, dd_server_t* out) {
   if (st == DD_ERR_DEVICE) st = DD_ERR_NOMEM;
   s->ranges.reset(c.hbm_budget_bytes);
   if (st == DD_OK) st = hip_status(hipStreamCreateWithFlags(&s->setup, hipStreamNonBlocking));
-  if (st == DD_OK && c.mode == DD_SERVE_BATCHED) st = hip_status(batch_set_lds(BATCH_LDS_MAX));
+  if (st == DD_OK && c.mode == DD_SERVE_BATCHED) st = hip_status(batch_set_lds(BATCH_LDS_MAX, batch_lds2_max()));
   if (st == DD_OK) {
     hipDeviceProp_t prop;
     st = hip_status(hipGetDeviceProperties(&prop, c.device));
-    if (st == DD_OK) s->grid = prop.multiProcessorCount * batch_max_blocks_per_cu(BATCH_LDS_MAX);
+    if (st == DD_OK) {
+      s->grid1 = prop.multiProcessorCount * batch_max_blocks_per_cu(0, BATCH_LDS_MAX);
+      s->grid2 = prop.multiProcessorCount * batch_max_blocks_per_cu(1, batch_lds2_max());
+    }
   }
   s->slots.resize(c.max_inflight);
   for (int i = 0; i < c.max_inflight && st == DD_OK; ++i) st = make_slot(s, s->slots[i]);
