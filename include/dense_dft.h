@@ -270,10 +270,11 @@ dd_status dense_dft_batch_sched_candidates(int64_t N, int32_t alpha, dd_sched *o
 
 /* Enqueue the whole batch on `stream`: a staging kernel that reads the
  * descriptor table from pinned host memory into device memory and clears the
- * two queue heads, then the persistent queue kernel (a fixed grid sized to
- * the device's occupancy; its blocks take tasks until the queue is empty)
- * over every single-pass and pass-1 task, then, if the batch has two-pass
- * signals, over every pass-2 task, so no block waits for another; then the
+ * two queue heads, then a persistent queue kernel (a fixed grid sized to the
+ * device's occupancy; its blocks take tasks until the queue is empty) over
+ * every single-pass and pass-1 task, then, if the batch has two-pass
+ * signals, a second, lighter one over every pass-2 task, so no block waits
+ * for another; then the
  * plain executions of the fallback signals.  Nothing synchronises, no memory
  * is allocated and no memset is enqueued, so the call can be captured in a
  * HIP graph; a replay re-reads the descriptor table at replay time.
