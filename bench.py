@@ -108,6 +108,27 @@ def tune_classes(dd, classes, batch_kernel=True, plain_batch=1):
     return out
 
 
+def precision_errors(dd, xd, Xd, N, alpha, T):
+    """The precision form: relative L2 error against the FP64 oracle on the
+    workload's 16384 seeded bins (tests/golden fixture written by the oracle)
+    with FP64-generated twiddles (Xd, the timed output) and with the
+    FP32-twiddle variant."""
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", "precision_2p22_a16_16384.npz")
+    fx = np.load(path, allow_pickle=False)
+    bins, ref = fx["bins"], fx["X"]
+    idx = torch.from_numpy(bins).to(Xd.device)
+    p32 = dd.dense_dft_plan(N, alpha, T, 1, dd.DD_C64, dd.DD_TWIDDLE_FP32)
+    X32 = torch.empty_like(Xd)
+    dd.dense_dft_exec(p32, xd, X32)
+    torch.cuda.synchronize()
+    out = {"bins": int(len(bins)), "bound": 1e-5, "reference": "FP64 oracle, " + os.path.relpath(path, ROOT)}
+    for name, X in (("rel_l2_fp64_twiddles", Xd), ("rel_l2_fp32_twiddles", X32)):
+        got = X[0][idx].cpu().numpy()
+        out[name] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return out
+
+
 def cpu_baseline(x0, alpha, T, M, N, target_s=12.0):
     """Time the FP64 oracle on a bounded bin sample of signal 0 (host cores)."""
     import oracle
@@ -418,6 +439,8 @@ def main():
                      "what": "whole transform per step (all its kernels): algorithmic bytes "
                              "batch*(N*s_in + alpha*N*s_out) / summed kernel durations"},
     }
+    if args.workload == "precision":
+        result["precision"] = precision_errors(dd, xd, Xd, N, alpha, T)
     if not args.no_cpu:
         x0 = x[0]
         bins, ref, cpu = cpu_baseline(x0, alpha, T, M, N)
