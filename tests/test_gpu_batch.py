@@ -150,3 +150,16 @@ def test_exec_many_and_fp64_fallback(oracle_mod):
     assert_close(X1.cpu().numpy()[bins], oracle_mod.alpha_dft_bins(x1, 4, 8.192, bins), "f32", "c64",
                  full_rms=spectrum_rms(x1, 8.192))
     assert_close(X2.cpu().numpy(), oracle_mod.alpha_dft(x2, 4, 1.024), "f64", "f64 fallback")
+
+
+def test_batch_fp32_twiddles(oracle_mod):
+    import torch
+    import paper_2403_16665_amd as dd
+    sigs = make_mix(17, 12, nmax=65536)
+    xs = [torch.from_numpy(x).cuda() for (_, _, _, x) in sigs]
+    Xs = [torch.empty(a * N, dtype=torch.complex64, device="cuda") for (N, a, _, _) in sigs]
+    b = dd.dense_dft_batch_plan([(N, a, N * 1e-3, c, xs[i], Xs[i]) for i, (N, a, c, _) in enumerate(sigs)],
+                                flags=dd.DD_TWIDDLE_FP32)
+    dd.dense_dft_batch_exec(b)
+    torch.cuda.synchronize()
+    check_against_oracle(oracle_mod, sigs, [X.cpu().numpy() for X in Xs])

@@ -220,3 +220,30 @@ def test_serve_batches_overlap_under_load():
     torch.cuda.synchronize()
     for i in range(0, count, 7):
         assert_same(Xs[i].cpu().numpy(), ref[i % 4].cpu().numpy(), f"request {i}")
+
+
+def test_serve_caller_stream_and_fp32_twiddles(oracle_mod):
+    """A server whose slots share the caller's stream, with the FP32-twiddle
+    variant: results match the oracle, and match a plain execution made with
+    the same twiddle flag."""
+    import torch
+    import paper_2403_16665_amd as dd
+    reqs = make_requests(36, 10, nmax=65536)
+    xs, Xs = device_buffers(reqs)
+    stream = torch.cuda.Stream()
+    srv = dd.dense_dft_server_create(hbm_budget_bytes=1 << 30, flags=dd.DD_TWIDDLE_FP32,
+                                     hip_stream=stream.cuda_stream)
+    dd.dense_dft_server_pause(srv, True)
+    tickets = [dd.dense_dft_submit(srv, (N, a, N * 1e-3, c, xs[i], Xs[i])) for i, (N, a, c, _) in enumerate(reqs)]
+    dd.dense_dft_server_pause(srv, False)
+    res = [dd.dense_dft_wait(srv, t, 30_000_000) for t in tickets]
+    assert all(r["status"] == 0 for r in res)
+    dd.dense_dft_server_destroy(srv)
+    rng = np.random.default_rng(13)
+    for i, (N, a, c, x) in enumerate(reqs):
+        got = Xs[i].cpu().numpy()
+        bins = siggen.bin_subset(rng, a * N, 128)
+        assert_close(got[bins], oracle_mod.alpha_dft_bins(x, a, N * 1e-3, bins), "f32",
+                     f"fp32-twiddle server N={N} alpha={a}", full_rms=spectrum_rms(x, N * 1e-3))
+        ref = dd.alpha_dft(xs[i], a, N * 1e-3, flags=dd.DD_TWIDDLE_FP32).cpu().numpy()
+        assert_same(got, ref, f"fp32-twiddle served vs plain, request {i}")
