@@ -54,7 +54,7 @@ typedef enum dd_dtype {
 typedef enum dd_status {
     DD_OK = 0,
     DD_ERR_INVALID = 1,      /* bad argument: null/misaligned pointer, N<1, T<=0, overlap ... */
-    DD_ERR_UNSUPPORTED = 2,  /* alpha not an integer >= 1, N with a prime factor > 5, size limits */
+    DD_ERR_UNSUPPORTED = 2,  /* alpha not an integer >= 1, N not of the built lengths, size limits */
     DD_ERR_NOMEM = 3,        /* device or host allocation failed */
     DD_ERR_DEVICE = 4,       /* a HIP runtime call failed */
     DD_ERR_BUSY = 5,         /* serving: queue full / result not ready */
@@ -89,7 +89,10 @@ typedef struct dd_plan *dd_plan_t;
  * generates the device twiddle tables on the current device, and
  * synchronises once.
  *   out    : receives the plan handle (NULL on failure).
- *   N      : samples per signal, 1 <= N, alpha*N <= 2^31.
+ *   N      : samples per signal: 2^a (a <= 24), 3*2^a (a <= 22) or 5*2^a
+ *            (a <= 21), the lengths the kernels are built for (N = N1*N2 with
+ *            N1 a power of two, 3 or 5 times one, up to 4096, and N2 a power
+ *            of two up to 4096); also alpha*N <= 2^31.
  *   alpha  : dense sampling factor, integer >= 1 (alpha < 1 and non-integer
  *            alpha -> DD_ERR_UNSUPPORTED).
  *   T      : finite, > 0.

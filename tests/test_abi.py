@@ -48,6 +48,8 @@ def test_binding_loads_and_names_match():
     (64, 0, 1.0, 1, 1, 0, 2),                # alpha < 1 (alpha < 1 is a one-way transform; unsupported)
     (64, -3, 1.0, 1, 1, 0, 2),
     (7, 2, 1.0, 1, 1, 0, 2),                 # prime factor > 5
+    (15 * 4096, 2, 1.0, 1, 1, 0, 2),         # 3 and 5 in one length: not a built length
+    (1 << 25, 2, 1.0, 1, 1, 0, 2),           # beyond 4096 x 4096
     (1 << 20, 4096, 1.0, 1, 1, 0, 2),        # alpha*N > 2^31
 ])
 def test_plan_rejects_bad_arguments(N, alpha, T, batch, dtype, flags, want):
