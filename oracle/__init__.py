@@ -10,7 +10,11 @@ eq. (2), sign convention of Section 3):
 
     X_m = (T/N) * sum_{n<N} x_n * exp(-2 pi i m n / (alpha N)),  m < alpha N
 
-in double precision, one output bin at a time (``dd_oracle.c``).
+in double precision, one output bin at a time (``dd_oracle.c``), and the
+inverse transform (eq. (7) second line, read with the 1/(alpha T) factor that
+undoes the forward one):
+
+    x_n = (1/(alpha T)) * sum_{m<alpha N} X_m * exp(+2 pi i m n / (alpha N)),  n < N
 
 Pins: every function here is checked against facts the paper and the
 mathematics fix, in ``tests/test_oracle_pins.py``.
@@ -52,6 +56,10 @@ def _load():
                                            ctypes.c_double, ip, ctypes.c_int64,
                                            dp, dp, ctypes.c_int]
         lib.dd_oracle_bins_mut.restype = ctypes.c_int
+        lib.dd_oracle_inv_mut.argtypes = [dp, dp, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_double, ip, ctypes.c_int64,
+                                          dp, dp, ctypes.c_int]
+        lib.dd_oracle_inv_mut.restype = ctypes.c_int
         lib.dd_oracle_threads.argtypes = []
         lib.dd_oracle_threads.restype = ctypes.c_int
         _lib = lib
@@ -96,3 +104,35 @@ def alpha_dft(x, alpha: int, T: float, *, mutation: int = 0) -> np.ndarray:
     N = np.asarray(x).shape[0]
     return alpha_dft_bins(x, alpha, T, np.arange(alpha * N, dtype=np.int64),
                           mutation=mutation)
+
+
+def inverse_alpha_dft_samples(X, alpha: int, T: float, samples, *, mutation: int = 0) -> np.ndarray:
+    """x_n of the inverse transform for the requested samples n (each in
+    [0, alpha*N), N = len(X) / alpha).  ``X`` is promoted exactly to
+    complex128; returns complex128.  ``mutation`` != 0 plants a known
+    mistake (for the pin self-test only)."""
+    Xa = np.asarray(X)
+    if Xa.ndim != 1 or Xa.shape[0] % int(alpha):
+        raise ValueError("X must be 1-D with alpha*N entries")
+    N = Xa.shape[0] // int(alpha)
+    Xr = np.ascontiguousarray(Xa.real, dtype=np.float64)
+    Xi = (np.ascontiguousarray(Xa.imag, dtype=np.float64) if np.iscomplexobj(Xa)
+          else np.zeros(Xa.shape[0], dtype=np.float64))
+    n = np.ascontiguousarray(np.asarray(samples, dtype=np.int64).reshape(-1))
+    outr = np.empty(n.shape[0], dtype=np.float64)
+    outi = np.empty(n.shape[0], dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int64)
+    rc = _load().dd_oracle_inv_mut(
+        Xr.ctypes.data_as(dp), Xi.ctypes.data_as(dp), N, int(alpha), float(T),
+        n.ctypes.data_as(ip), n.shape[0], outr.ctypes.data_as(dp),
+        outi.ctypes.data_as(dp), int(mutation))
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    return outr + 1j * outi
+
+
+def inverse_alpha_dft(X, alpha: int, T: float, *, mutation: int = 0) -> np.ndarray:
+    """All N samples of the inverse transform, n = 0 .. N-1."""
+    N = np.asarray(X).shape[0] // int(alpha)
+    return inverse_alpha_dft_samples(X, alpha, T, np.arange(N, dtype=np.int64), mutation=mutation)

@@ -118,6 +118,68 @@ int dd_oracle_bins_mut(const double *xr, const double *xi, int64_t N,
     return 0;
 }
 
+/* The inverse alpha-transform (the reading of eq. (7), second line, with the
+ * 1/(alpha T) factor that makes it undo the forward transform of eq. (2)):
+ *     x_n = (1/(alpha T)) * sum_{m < alpha N} X_m * exp(+2 pi i m n / (alpha N)),
+ * evaluated at the requested samples n (0 <= n < alpha N; the transform of a
+ * forward spectrum vanishes for n >= N).  Direct FP64 sum, exact integer
+ * phase q = (m n) mod alpha N.  Mutations (for the tests that check the pins
+ * reject a wrong inverse): 1 wrong exponent sign, 2 factor 1/T (alpha
+ * dropped), 3 sum over m < N only, 4 spectrum index off by one.
+ * Returns 0 on success, -1 on invalid arguments, -2 on allocation failure. */
+int dd_oracle_inv_mut(const double *Xr, const double *Xi, int64_t N, int64_t alpha,
+                      double T, const int64_t *samples, int64_t ns, double *outr,
+                      double *outi, int mutation)
+{
+    if (N < 1 || alpha < 1 || ns < 0 || !Xr || !Xi || (ns && (!samples || !outr || !outi)))
+        return -1;
+    const int64_t M = alpha * N;
+    for (int64_t b = 0; b < ns; ++b)
+        if (samples[b] < 0 || samples[b] >= M) return -1;
+    double *tc = NULL, *ts = NULL;
+    if (M <= ORACLE_TABLE_MAX) {
+        tc = (double *)malloc(sizeof(double) * (size_t)M);
+        ts = (double *)malloc(sizeof(double) * (size_t)M);
+        if (!tc || !ts) { free(tc); free(ts); return -2; }
+        #pragma omp parallel for schedule(static)
+        for (int64_t q = 0; q < M; ++q) {
+            double th = TWO_PI * ((double)q / (double)M);
+            tc[q] = cos(th);
+            ts[q] = sin(th);
+        }
+    }
+    const double scale = (mutation == 2) ? 1.0 / T : 1.0 / ((double)alpha * T);
+    const int64_t mlast = (mutation == 3) ? N : M;
+
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < ns; ++b) {
+        const int64_t n = samples[b];
+        double ar = 0.0, ai = 0.0;
+        uint64_t q = 0;                           /* q = (m*n) mod M */
+        for (int64_t m = 0; m < mlast; ++m) {
+            double c, s;
+            if (tc) { c = tc[q]; s = ts[q]; }
+            else {
+                double th = TWO_PI * ((double)q / (double)M);
+                c = cos(th); s = sin(th);
+            }
+            if (mutation == 1) s = -s;
+            const int64_t src = (mutation == 4) ? (m + 1) % M : m;
+            const double pr = Xr[src], pi = Xi[src];
+            /* X_m * (cos th + i sin th) */
+            ar += pr * c - pi * s;
+            ai += pi * c + pr * s;
+            q += (uint64_t)n;
+            if (q >= (uint64_t)M) q -= (uint64_t)M;
+        }
+        outr[b] = scale * ar;
+        outi[b] = scale * ai;
+    }
+    free(tc);
+    free(ts);
+    return 0;
+}
+
 int dd_oracle_bins(const double *xr, const double *xi, int64_t N, int64_t alpha,
                    double T, const int64_t *bins, int64_t nbins, double *outr,
                    double *outi)

@@ -271,3 +271,55 @@ def test_generators_deterministic():
     mix = siggen.uneven_mix(siggen.rngs(3, 1)[0], 1000)
     assert len(mix) == 1000
     assert all(n in siggen.uneven_sizes() and a in siggen.UNEVEN_ALPHAS for n, a in mix)
+
+
+# --- the oracle's inverse transform (eq. (7) second line, 1/(alpha T)) ---
+@pytest.mark.parametrize("N,alpha", [(16, 1), (12, 3), (25, 4), (40, 8)])
+def test_inverse_against_library_ifft(oracle_mod, N, alpha):
+    """x_n = (1/(alpha T)) sum_m X_m e^{+2 pi i mn/(alpha N)} = (N/T) ifft(X)_n
+    for any spectrum X, not only forward spectra (numpy's ifft carries 1/(alpha N))."""
+    rng = np.random.default_rng(7 * N + alpha)
+    X = rand_c(rng, alpha * N)
+    T = 1.7
+    got = oracle_mod.inverse_alpha_dft_samples(X, alpha, T, np.arange(alpha * N))
+    ref = np.fft.ifft(X) * (N / T)
+    assert rel(got, ref) < TOL
+
+
+@pytest.mark.parametrize("N,alpha", [(8, 1), (24, 2), (20, 5), (64, 16)])
+def test_inverse_round_trip_and_vanishing_tail(oracle_mod, N, alpha):
+    """The inverse undoes the forward transform on the N samples, and the
+    samples N <= n < alpha N of the same sum vanish (the padded zeros)."""
+    rng = np.random.default_rng(N + alpha)
+    x = rand_c(rng, N)
+    T = 0.9
+    X = oracle_mod.alpha_dft(x, alpha, T)
+    assert rel(oracle_mod.inverse_alpha_dft(X, alpha, T), x) < TOL
+    if alpha > 1:
+        tail = oracle_mod.inverse_alpha_dft_samples(X, alpha, T, np.arange(N, alpha * N))
+        assert np.max(np.abs(tail)) < 1e-12 * np.max(np.abs(x))
+
+
+def test_inverse_single_bin_closed_form(oracle_mod):
+    """X = delta at m0: x_n = e^{2 pi i m0 n/(alpha N)} / (alpha T)."""
+    N, alpha, T, m0 = 30, 4, 2.5, 37
+    X = np.zeros(alpha * N, dtype=np.complex128)
+    X[m0] = 1.0
+    n = np.arange(N)
+    ref = np.exp(2j * np.pi * m0 * n / (alpha * N)) / (alpha * T)
+    assert rel(oracle_mod.inverse_alpha_dft(X, alpha, T), ref) < TOL
+
+
+@pytest.mark.parametrize("mutation", [1, 2, 3, 4])
+def test_inverse_pins_reject_planted_mistakes(oracle_mod, mutation):
+    """Each planted mistake of the inverse fails at least one of the pins above."""
+    rng = np.random.default_rng(99)
+    N, alpha, T = 24, 3, 1.3
+    X = rand_c(rng, alpha * N)
+    x = rand_c(rng, N)
+    fails = []
+    got = oracle_mod.inverse_alpha_dft_samples(X, alpha, T, np.arange(alpha * N), mutation=mutation)
+    fails.append(rel(got, np.fft.ifft(X) * (N / T)) >= TOL)
+    Xf = oracle_mod.alpha_dft(x, alpha, T)
+    fails.append(rel(oracle_mod.inverse_alpha_dft(Xf, alpha, T, mutation=mutation), x) >= TOL)
+    assert any(fails)
