@@ -123,6 +123,27 @@ dd_status dense_dft_workspace_size(dd_plan_t plan, size_t *bytes);
 dd_status dense_dft_exec(dd_plan_t plan, const void *x, void *X,
                          void *workspace, void *stream);
 
+/* Enqueue the inverse transform of all `batch` spectra of the plan on
+ * `stream` (the reading of eq. (7), second line, with the factor 1/(alpha T)
+ * that undoes the forward transform of eq. (2)):
+ *     x_n = (1/(alpha T)) * sum_{m<alpha N} X_m * exp(+2 pi i m n / (alpha N)),
+ *     n = 0 .. N-1,
+ * computed as the adjoint of the plan's schedule: alpha length-N transforms
+ * of the subsequences X_{alpha k + j}, each times W_{alpha N}^{-jn}, summed
+ * over j (with the plan's own twiddle tables).
+ *   X         : device, [batch][alpha*N] complex64 (plans of DD_F32 / DD_C64)
+ *               or complex128 (DD_F64 / DD_C128), aligned to its element.
+ *   x         : device, [batch][N] complex output of the same precision (also
+ *               for plans of real input); must not overlap X.
+ *   workspace : as dense_dft_exec (the same size serves both directions).
+ *   stream    : hipStream_t, NULL for the default stream.
+ * Profiled launches (dense_dft_profile_begin) report kinds 4 (one pass),
+ * 5 (pass A) and 6 (pass B).
+ * Errors: DD_ERR_INVALID (null / misaligned / overlapping pointers),
+ *         DD_ERR_DEVICE (kernel launch failed). */
+dd_status dense_dft_exec_inverse(dd_plan_t plan, const void *X, void *x,
+                                 void *workspace, void *stream);
+
 /* Free the plan's device tables and workspace (synchronises its device). */
 dd_status dense_dft_destroy(dd_plan_t plan);
 

@@ -40,6 +40,8 @@ _lib.dense_dft_plan.argtypes = [ctypes.POINTER(_vp), _i64, ctypes.c_int32, ctype
 _lib.dense_dft_plan.restype = ctypes.c_int
 _lib.dense_dft_exec.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.dense_dft_exec.restype = ctypes.c_int
+_lib.dense_dft_exec_inverse.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.dense_dft_exec_inverse.restype = ctypes.c_int
 _lib.dense_dft_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
 _lib.dense_dft_workspace_size.restype = ctypes.c_int
 _lib.dense_dft_destroy.argtypes = [_vp]
@@ -204,7 +206,7 @@ def dense_dft_exec(plan: Plan, x, X, workspace=None, stream=None) -> None:
            "dense_dft_exec")
 
 
-KERNEL_KINDS = {1: "single", 2: "pass1", 3: "pass2"}
+KERNEL_KINDS = {1: "single", 2: "pass1", 3: "pass2", 4: "inverse_single", 5: "inverse_passA", 6: "inverse_passB"}
 
 
 def dense_dft_profile_begin(plan: Plan, max_launches: int) -> None:
@@ -556,6 +558,36 @@ def dtype_code(torch_dtype) -> int:
 def out_dtype(code: int):
     import torch
     return torch.complex64 if code in (DD_F32, DD_C64) else torch.complex128
+
+
+def dense_dft_exec_inverse(plan: Plan, X, x, workspace=None, stream=None) -> None:
+    """Inverse transform of device spectra X ([batch][alpha*N]) into x ([batch][N] complex)."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    ws = None if workspace is None else workspace.data_ptr()
+    _check(_lib.dense_dft_exec_inverse(plan.handle, X.data_ptr(), x.data_ptr(), ws, _vp(stream)),
+           "dense_dft_exec_inverse")
+
+
+def alpha_idft(X, alpha: int, T: float, flags: int = DD_TWIDDLE_FP64, plan: Plan | None = None):
+    """x = inverse alpha-dense DFT of the rows of device tensor X ([batch, alpha*N] or [alpha*N],
+    complex64 or complex128): x_n = (1/(alpha T)) sum_m X_m exp(+2 pi i m n/(alpha N)), n < N."""
+    import torch
+    squeeze = X.dim() == 1
+    X2 = (X.reshape(1, -1) if squeeze else X).contiguous()
+    batch, M = X2.shape
+    if M % alpha:
+        raise ValueError("the spectrum length must be a multiple of alpha")
+    N = M // alpha
+    code = DD_C64 if X2.dtype == torch.complex64 else DD_C128 if X2.dtype == torch.complex128 else None
+    if code is None:
+        raise TypeError(f"unsupported spectrum dtype {X2.dtype}")
+    if plan is None:
+        plan = dense_dft_plan(N, alpha, T, batch, code, flags)
+    x = torch.empty((batch, N), dtype=X2.dtype, device=X2.device)
+    dense_dft_exec_inverse(plan, X2, x)
+    return x[0] if squeeze else x
 
 
 def alpha_dft(x, alpha: int, T: float, flags: int = DD_TWIDDLE_FP64, plan: Plan | None = None):

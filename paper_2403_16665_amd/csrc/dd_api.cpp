@@ -14,6 +14,7 @@
 
 #include "../../include/dense_dft.h"
 #include "dd_host.hpp"
+#include "dd_inverse.hpp"
 #include "dd_launch.hpp"
 #include "dd_tune.hpp"
 
@@ -37,6 +38,9 @@ struct dd_plan {
   size_t p1_lds = 0;
   int p2_lines = 1, p2_TL = 1, p2_ntile = 1;
   size_t p2_lds = 0;
+  // inverse pass B (every j per block): pre-twiddles staged in LDS, its LDS
+  int inv_pre_lds = 0;
+  size_t inv_p1_lds = 0;
   int64_t chunk = 1;
   // device tables (element type cx<float> or cx<double>)
   void* twL1 = nullptr;   // stage twiddles of the N1 (or N) line FFT
@@ -211,6 +215,10 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
   p->p1_pre_lds = pre_bytes <= 16 * 1024 &&
                   lds_pass1((int)N1, g1.lines, p->rbytes, jg * (int)N1) <= (size_t)LDS_PASS_MAX ? 1 : 0;
   p->p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, p->p1_pre_lds ? jg * (int)N1 : 0);
+  const size_t inv_pre = (size_t)alpha * N1 * cx_bytes(p);
+  p->inv_pre_lds =
+      inv_pre <= 16 * 1024 && lds_pass1((int)N1, g1.lines, p->rbytes, alpha * (int)N1) <= (size_t)LDS_PASS_MAX ? 1 : 0;
+  p->inv_p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, p->inv_pre_lds ? alpha * (int)N1 : 0);
   p->ws_bytes = (size_t)chunk * per_sig;
   return DD_OK;
 }
@@ -457,6 +465,59 @@ dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s
   return DD_OK;
 }
 
+// The inverse transform: the adjoint of the forward schedule, with the same
+// tables and geometry (kinds 4, 5, 6 in the profile: one pass, pass A, pass B).
+template <typename R>
+dd_status exec_inverse_typed(dd_plan* p, const cx<R>* X, cx<R>* x, cx<R>* ws, hipStream_t s) {
+  const R scale = (R)(1.0 / ((double)p->alpha * p->T));
+  const int64_t M = (int64_t)p->alpha * p->N;
+  if (p->passes == 1) {
+    DenseArgs<R> a{};
+    a.batch = p->batch;
+    a.x_stride = p->N;
+    a.y_stride = M;
+    a.N1 = (int)p->N;
+    a.N2 = 1;
+    a.alpha = p->alpha;
+    a.lines = p->s_lines;
+    a.scale = scale;
+    a.twL = static_cast<const cx<R>*>(p->twL1);
+    a.twPre = static_cast<const cx<R>*>(p->twPre);
+    LaunchCfg c{(p->batch + p->s_lines - 1) / p->s_lines, p->s_lines * p->s_TL, p->s_lds, s};
+    return hip_status(timed_launch(p, 4, s, [&] { return launch_single_inv((int)p->N, c, X, x, a); }));
+  }
+  for (int64_t c0 = 0; c0 < p->batch; c0 += p->chunk) {
+    const int64_t nb = p->batch - c0 < p->chunk ? p->batch - c0 : p->chunk;
+    DenseArgs<R> a{};
+    a.batch = nb;
+    a.x_stride = p->N;
+    a.y_stride = M;
+    a.N1 = (int)p->N1;
+    a.N2 = (int)p->N2;
+    a.alpha = p->alpha;
+    a.scale = scale;
+    a.twPre = static_cast<const cx<R>*>(p->twPre);
+    a.twQ = static_cast<const cx<R>*>(p->twQ);
+    a.twPost = static_cast<const cx<R>*>(p->twPost);
+    DenseArgs<R> aA = a;
+    aA.lines = p->p2_lines;
+    aA.ntile = p->p2_ntile;
+    aA.twL = static_cast<const cx<R>*>(p->twL2);
+    LaunchCfg cA{nb * p->p2_ntile, p->p2_lines * p->p2_TL, p->p2_lds, s};
+    hipError_t e = timed_launch(p, 5, s, [&] { return launch_passA((int)p->N2, cA, X + c0 * M, ws, aA); });
+    if (e != hipSuccess) return hip_status(e);
+    DenseArgs<R> aB = a;
+    aB.lines = p->p1_lines;
+    aB.ntile = p->p1_ntile;
+    aB.pre_lds = p->inv_pre_lds;
+    aB.twL = static_cast<const cx<R>*>(p->twL1);
+    LaunchCfg cB{nb * p->p1_ntile, p->p1_lines * p->p1_TL, p->inv_p1_lds, s};
+    e = timed_launch(p, 6, s, [&] { return launch_passB((int)p->N1, cB, ws, x + c0 * p->N, aB); });
+    if (e != hipSuccess) return hip_status(e);
+  }
+  return DD_OK;
+}
+
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
   return x < y + nb && y < x + na;
@@ -496,6 +557,26 @@ dd_status dense_dft_exec(dd_plan_t p, const void* x, void* X, void* workspace, v
                                 static_cast<cx<double>*>(ws), s);
   }
   return DD_ERR_INVALID;
+}
+
+dd_status dense_dft_exec_inverse(dd_plan_t p, const void* X, void* x, void* workspace, void* stream) {
+  if (!p || !X || !x) return DD_ERR_INVALID;
+  const size_t cxb = cx_bytes(p);
+  if ((uintptr_t)X % cxb != 0 || (uintptr_t)x % cxb != 0) return DD_ERR_INVALID;
+  const size_t in_total = (size_t)p->batch * p->alpha * p->N * cxb;
+  const size_t out_total = (size_t)p->batch * p->N * cxb;
+  if (overlaps(X, in_total, x, out_total)) return DD_ERR_INVALID;
+  void* ws = workspace ? workspace : p->ws;
+  if (p->passes == 2) {
+    if (!ws || (uintptr_t)ws % cxb != 0) return DD_ERR_INVALID;
+    if (overlaps(ws, p->ws_bytes, X, in_total) || overlaps(ws, p->ws_bytes, x, out_total)) return DD_ERR_INVALID;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->dbl)
+    return exec_inverse_typed<double>(p, static_cast<const cx<double>*>(X), static_cast<cx<double>*>(x),
+                                      static_cast<cx<double>*>(ws), s);
+  return exec_inverse_typed<float>(p, static_cast<const cx<float>*>(X), static_cast<cx<float>*>(x),
+                                   static_cast<cx<float>*>(ws), s);
 }
 
 dd_status dense_dft_destroy(dd_plan_t p) {
