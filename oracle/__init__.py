@@ -136,3 +136,15 @@ def inverse_alpha_dft(X, alpha: int, T: float, *, mutation: int = 0) -> np.ndarr
     """All N samples of the inverse transform, n = 0 .. N-1."""
     N = np.asarray(X).shape[0] // int(alpha)
     return inverse_alpha_dft_samples(X, alpha, T, np.arange(N, dtype=np.int64), mutation=mutation)
+
+
+def decimated_dft(x, p: int, T: float, *, mutation: int = 0) -> np.ndarray:
+    """The transform for alpha = 1/p (p a positive divisor of N; Section 2, the
+    case alpha < 1): X_m = (T/N) sum_{n<N} x_n exp(-2 pi i m n / (N/p)),
+    m < N/p.  Since exp(-2 pi i m n p / N) is the alpha = 1 kernel at bin p m,
+    the definition is evaluated as the alpha = 1 sum at bins p m.  Returns
+    complex128."""
+    N = np.asarray(x).shape[0]
+    if p < 1 or N % p:
+        raise ValueError("p must be a positive divisor of N")
+    return alpha_dft_bins(x, 1, T, np.arange(N // p, dtype=np.int64) * p, mutation=mutation)

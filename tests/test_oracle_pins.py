@@ -323,3 +323,23 @@ def test_inverse_pins_reject_planted_mistakes(oracle_mod, mutation):
     Xf = oracle_mod.alpha_dft(x, alpha, T)
     fails.append(rel(oracle_mod.inverse_alpha_dft(Xf, alpha, T, mutation=mutation), x) >= TOL)
     assert any(fails)
+
+
+# --- alpha = 1/p (Section 2, alpha < 1) ---
+@pytest.mark.parametrize("N,p", [(12, 1), (12, 3), (40, 4), (60, 5), (64, 16)])
+def test_decimated_against_library_fft(oracle_mod, N, p):
+    """X_m = (T/N) sum_n x_n e^{-2 pi i mn/(N/p)} is the textbook DFT at every
+    p-th bin, and also the DFT of length N/p of the folded sequence
+    x'_r = sum_k x_{r + k N/p} (the periodicity the paper's alpha < 1 case uses)."""
+    rng = np.random.default_rng(N * p)
+    x = rand_c(rng, N)
+    T = 2.2
+    got = oracle_mod.decimated_dft(x, p, T)
+    assert rel(got, np.fft.fft(x)[::p] * T / N) < TOL
+    folded = x.reshape(p, N // p).sum(axis=0)
+    assert rel(got, np.fft.fft(folded) * T / N) < TOL
+
+
+def test_decimated_rejects_non_divisor(oracle_mod):
+    with pytest.raises(ValueError):
+        oracle_mod.decimated_dft(np.ones(10), 3, 1.0)
