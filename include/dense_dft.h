@@ -103,6 +103,22 @@ typedef struct dd_plan *dd_plan_t;
 dd_status dense_dft_plan(dd_plan_t *out, int64_t N, int32_t alpha, double T,
                          int64_t batch, dd_dtype dtype, uint32_t flags);
 
+/* Plan the transform with alpha = 1/p (Section 2, the case alpha < 1): N
+ * samples to N/p bins spaced p/T apart,
+ *     X_m = (T/N) * sum_{n<N} x_n * exp(-2 pi i m n / (N/p)),  m < N/p.
+ * The kernel has period N/p in n, so an execution folds the signal,
+ * x'_r = sum_{k<p} x_{r + k N/p} (into the workspace, summed in double
+ * precision), then runs the plain transform of length N/p (a plan with
+ * alpha = 1, chosen by the planner or the tuning table).  A one-way
+ * transform: dense_dft_exec_inverse returns DD_ERR_UNSUPPORTED.
+ *   p      : integer >= 1 dividing N; N/p must be a built length (as N of
+ *            dense_dft_plan).  p = 1 gives the plain alpha = 1 plan.
+ *   Other arguments and errors as dense_dft_plan; the plan executes with
+ *   dense_dft_exec (x [batch][N], X [batch][N/p]); its workspace holds the
+ *   folded signals as well. */
+dd_status dense_dft_plan_decimated(dd_plan_t *out, int64_t N, int32_t p, double T,
+                                   int64_t batch, dd_dtype dtype, uint32_t flags);
+
 /* Bytes of device scratch one execution needs (0 for single-pass plans).
  * The plan owns a default workspace of this size unless it was created with
  * DD_NO_WORKSPACE. */

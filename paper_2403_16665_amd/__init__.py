@@ -40,6 +40,9 @@ _lib.dense_dft_plan.argtypes = [ctypes.POINTER(_vp), _i64, ctypes.c_int32, ctype
 _lib.dense_dft_plan.restype = ctypes.c_int
 _lib.dense_dft_exec.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.dense_dft_exec.restype = ctypes.c_int
+_lib.dense_dft_plan_decimated.argtypes = [ctypes.POINTER(_vp), _i64, ctypes.c_int32, ctypes.c_double, _i64,
+                                          ctypes.c_int, ctypes.c_uint32]
+_lib.dense_dft_plan_decimated.restype = ctypes.c_int
 _lib.dense_dft_exec_inverse.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.dense_dft_exec_inverse.restype = ctypes.c_int
 _lib.dense_dft_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -558,6 +561,31 @@ def dtype_code(torch_dtype) -> int:
 def out_dtype(code: int):
     import torch
     return torch.complex64 if code in (DD_F32, DD_C64) else torch.complex128
+
+
+def dense_dft_plan_decimated(N: int, p: int, T: float, batch: int, dtype: int,
+                             flags: int = DD_TWIDDLE_FP64) -> Plan:
+    """Plan of the alpha = 1/p transform (N samples to N/p bins)."""
+    h = _vp()
+    _check(_lib.dense_dft_plan_decimated(ctypes.byref(h), int(N), int(p), float(T), int(batch), int(dtype),
+                                         int(flags)), "dense_dft_plan_decimated")
+    plan = Plan(h, N, 1, T, batch, dtype, flags)
+    plan.p = int(p)
+    return plan
+
+
+def decimated_dft(x, p: int, T: float, flags: int = DD_TWIDDLE_FP64, plan: Plan | None = None):
+    """X = the alpha = 1/p transform of the rows of device tensor x ([batch, N] or [N])."""
+    import torch
+    squeeze = x.dim() == 1
+    x2 = (x.reshape(1, -1) if squeeze else x).contiguous()
+    batch, N = x2.shape
+    code = dtype_code(x2.dtype)
+    if plan is None:
+        plan = dense_dft_plan_decimated(N, p, T, batch, code, flags)
+    X = torch.empty((batch, N // p), dtype=out_dtype(code), device=x2.device)
+    dense_dft_exec(plan, x2, X)
+    return X[0] if squeeze else X
 
 
 def dense_dft_exec_inverse(plan: Plan, X, x, workspace=None, stream=None) -> None:

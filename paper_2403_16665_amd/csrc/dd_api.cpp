@@ -20,6 +20,11 @@
 
 using namespace dd;
 
+namespace dd {
+hipError_t launch_fold(dd_dtype dtype, const void* x, void* y, int64_t batch, int64_t N, int64_t Np, int p,
+                       hipStream_t s);  // dd_fold.hip
+}
+
 struct dd_plan {
   int device = 0;
   int64_t N = 0, N1 = 0, N2 = 1, batch = 0;
@@ -41,6 +46,11 @@ struct dd_plan {
   // inverse pass B (every j per block): pre-twiddles staged in LDS, its LDS
   int inv_pre_lds = 0;
   size_t inv_p1_lds = 0;
+  // alpha = 1/dec_p (dec_p > 1): the fold into the workspace, then the plain
+  // plan `inner` of length N/dec_p
+  int dec_p = 1;
+  dd_plan* inner = nullptr;
+  size_t fold_bytes = 0;
   int64_t chunk = 1;
   // device tables (element type cx<float> or cx<double>)
   void* twL1 = nullptr;   // stage twiddles of the N1 (or N) line FFT
@@ -336,7 +346,56 @@ dd_status dense_dft_plan_sched(dd_plan_t* out, int64_t N, int32_t alpha, double 
 
 dd_status dense_dft_plan_get_sched(dd_plan_t p, dd_sched* out) {
   if (!p || !out) return DD_ERR_INVALID;
-  *out = resolved(p);
+  *out = resolved(p->inner ? p->inner : p);
+  return DD_OK;
+}
+
+dd_status dense_dft_plan_decimated(dd_plan_t* out, int64_t N, int32_t p, double T, int64_t batch, dd_dtype dtype,
+                                   uint32_t flags) {
+  if (!out) return DD_ERR_INVALID;
+  *out = nullptr;
+  if (N < 1 || batch < 1 || !(T > 0.0) || !std::isfinite(T)) return DD_ERR_INVALID;
+  if (dtype != DD_F32 && dtype != DD_C64 && dtype != DD_F64 && dtype != DD_C128) return DD_ERR_INVALID;
+  if (flags & ~(uint32_t)(DD_TWIDDLE_FP32 | DD_NO_WORKSPACE)) return DD_ERR_INVALID;
+  if (p < 1 || N % p != 0) return DD_ERR_UNSUPPORTED;
+  if (p == 1) return plan_build(out, N, 1, T, batch, dtype, flags, nullptr);
+  const int64_t Np = N / p;
+  if (batch > INT64_MAX / N) return DD_ERR_UNSUPPORTED;
+  // the inner plan's factor T'/N' with T' = T/p is the transform's T/N
+  dd_plan_t in = nullptr;
+  dd_status st = plan_build(&in, Np, 1, T / p, batch, dtype, flags | DD_NO_WORKSPACE, nullptr);
+  if (st != DD_OK) return st;
+  dd_plan* w = new (std::nothrow) dd_plan;
+  if (!w) {
+    dense_dft_destroy(in);
+    return DD_ERR_NOMEM;
+  }
+  w->device = in->device;
+  w->N = N;
+  w->alpha = 1;
+  w->T = T;
+  w->batch = batch;
+  w->dtype = dtype;
+  w->flags = flags;
+  w->dbl = in->dbl;
+  w->rbytes = in->rbytes;
+  w->in_bytes = in->in_bytes;
+  w->passes = in->passes;
+  w->N1 = in->N1;
+  w->N2 = in->N2;
+  w->dec_p = p;
+  w->inner = in;
+  w->fold_bytes = ((size_t)batch * Np * in->in_bytes + 255) / 256 * 256;
+  w->ws_bytes = w->fold_bytes + in->ws_bytes;
+  if (!(flags & DD_NO_WORKSPACE)) {
+    st = hip_status(hipMalloc(&w->ws, w->ws_bytes));
+    if (st != DD_OK) {
+      dense_dft_destroy(in);
+      delete w;
+      return st == DD_ERR_DEVICE ? DD_ERR_NOMEM : st;
+    }
+  }
+  *out = w;
   return DD_OK;
 }
 
@@ -529,6 +588,21 @@ extern "C" {
 
 dd_status dense_dft_exec(dd_plan_t p, const void* x, void* X, void* workspace, void* stream) {
   if (!p || !x || !X) return DD_ERR_INVALID;
+  if (p->inner) {
+    // alpha = 1/p: fold into the workspace, then the plain length-N/p plan
+    const size_t in_total = (size_t)p->batch * p->N * p->in_bytes;
+    const size_t out_total = (size_t)p->batch * p->inner->N * cx_bytes(p);
+    if ((uintptr_t)x % p->in_bytes != 0 || (uintptr_t)X % cx_bytes(p) != 0) return DD_ERR_INVALID;
+    if (overlaps(x, in_total, X, out_total)) return DD_ERR_INVALID;
+    void* ws = workspace ? workspace : p->ws;
+    if (!ws || (uintptr_t)ws % 16 != 0) return DD_ERR_INVALID;
+    if (overlaps(ws, p->ws_bytes, x, in_total) || overlaps(ws, p->ws_bytes, X, out_total)) return DD_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e = launch_fold(p->dtype, x, ws, p->batch, p->N, p->inner->N, p->dec_p, s);
+    if (e != hipSuccess) return hip_status(e);
+    void* iws = p->inner->ws_bytes ? static_cast<char*>(ws) + p->fold_bytes : nullptr;
+    return dense_dft_exec(p->inner, ws, X, iws, stream);
+  }
   const size_t out_cx = cx_bytes(p);
   const size_t in_align = p->in_bytes;
   if ((uintptr_t)x % in_align != 0 || (uintptr_t)X % out_cx != 0) return DD_ERR_INVALID;
@@ -561,6 +635,7 @@ dd_status dense_dft_exec(dd_plan_t p, const void* x, void* X, void* workspace, v
 
 dd_status dense_dft_exec_inverse(dd_plan_t p, const void* X, void* x, void* workspace, void* stream) {
   if (!p || !X || !x) return DD_ERR_INVALID;
+  if (p->inner) return DD_ERR_UNSUPPORTED;  // alpha < 1 is a one-way transform (the fold loses information)
   const size_t cxb = cx_bytes(p);
   if ((uintptr_t)X % cxb != 0 || (uintptr_t)x % cxb != 0) return DD_ERR_INVALID;
   const size_t in_total = (size_t)p->batch * p->alpha * p->N * cxb;
@@ -588,12 +663,14 @@ dd_status dense_dft_destroy(dd_plan_t p) {
   free_events(p);
   free_tables(p);
   (void)hipSetDevice(cur);
+  if (p->inner) dense_dft_destroy(p->inner);
   delete p;
   return DD_OK;
 }
 
 dd_status dense_dft_profile_begin(dd_plan_t p, int32_t max_launches) {
   if (!p || max_launches < 1) return DD_ERR_INVALID;
+  if (p->inner) return dense_dft_profile_begin(p->inner, max_launches);
   free_events(p);
   try {
     p->prof_ev.resize(2 * (size_t)max_launches, nullptr);
@@ -616,6 +693,7 @@ dd_status dense_dft_profile_begin(dd_plan_t p, int32_t max_launches) {
 
 dd_status dense_dft_profile_end(dd_plan_t p, int32_t* kinds, float* ms, int32_t cap, int32_t* count) {
   if (!p || !count || (cap > 0 && (!kinds || !ms))) return DD_ERR_INVALID;
+  if (p->inner) return dense_dft_profile_end(p->inner, kinds, ms, cap, count);
   dd_status st = DD_OK;
   const int n = p->prof_n;
   if (n > 0 && hipEventSynchronize(p->prof_ev[2 * n - 1]) != hipSuccess) st = DD_ERR_DEVICE;

@@ -95,3 +95,12 @@ def test_batch_plan_rejects_bad_descriptors():
         assert dd._lib.dense_dft_batch_plan(ctypes.byref(h), (dd.dd_desc * 1)(bad), 1, 0) == 2
     assert dd._lib.dense_dft_batch_exec(None, None) == 1
     assert dd._lib.dense_dft_batch_destroy(None) == 1
+
+
+@pytest.mark.parametrize("N,p,want", [(12, 0, 2), (12, 5, 2), (61440 * 4, 4, 2), (0, 1, 1)])
+def test_decimated_plan_rejects(N, p, want):
+    import ctypes
+    import paper_2403_16665_amd as dd
+    h = ctypes.c_void_p(3)
+    assert dd._lib.dense_dft_plan_decimated(ctypes.byref(h), N, p, 1.0, 1, dd.DD_C64, 0) == want
+    assert not h.value
