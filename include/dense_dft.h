@@ -94,7 +94,8 @@ typedef struct dd_plan *dd_plan_t;
  *            N1 a power of two, 3 or 5 times one, up to 4096, and N2 a power
  *            of two up to 4096); also alpha*N <= 2^31.
  *   alpha  : dense sampling factor, integer >= 1 (alpha < 1 and non-integer
- *            alpha -> DD_ERR_UNSUPPORTED).
+ *            alpha -> DD_ERR_UNSUPPORTED; alpha = 1/p has its own plan,
+ *            dense_dft_plan_decimated).
  *   T      : finite, > 0.
  *   batch  : number of signals, >= 1, batch*alpha*N must fit int64.
  *   dtype  : input dtype (see above).
