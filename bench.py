@@ -529,7 +529,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="use the planner's built-in schedule rules instead of tuning first")
-    ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000,100000,200000,400000",
+    ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000,100000,200000,400000,800000",
                     help="serving: Poisson arrival rates (requests/s)")
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests per rate")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",

@@ -354,13 +354,15 @@ dd_status dense_dft_exec_many(const dd_desc *descs, int32_t count,
  * with a stream, an event and a HIP graph of the persistent batch launch
  * captured once at creation (its descriptor table is re-read from pinned
  * host memory at every replay, so one graph serves batches of any mix).
- * A scheduler thread takes queued requests in arrival order whenever a slot
- * is free, as many as the batch size and the memory budget admit, and
- * launches them as one batch while earlier batches still run on the other
- * slots.  Requests above batch_max_bins, the ones the batch kernel is not
- * built for, and a request alone in its batch (unless
- * DD_SERVE_DETERMINISTIC) run as plain executions of resident plans, with
- * the schedules the tuner recorded.  A request's footprint is its input and
+ * A scheduler thread fills a slot whenever one is free.  Requests above
+ * batch_max_bins and the ones the batch kernel is not built for run as
+ * plain executions of resident plans (with the schedules the tuner
+ * recorded), each in a slot of its own when it reaches the head of the
+ * queue, so that it overlaps the batches on the other slots.  Otherwise
+ * the slot takes the queued kernel requests in arrival order, stepping over
+ * the plain ones, as many as the batch size and the memory budget admit,
+ * and launches them as one batch.  A request alone in its batch runs as a
+ * plain execution too, unless DD_SERVE_DETERMINISTIC.  A request's footprint is its input and
  * output bytes plus its scratch; the footprints of admitted, unfinished requests never sum past
  * hbm_budget_bytes.  Each request is the transform of one dd_desc (the
  * problem of Section 2 for one signal); x and X are the caller's device
@@ -385,7 +387,7 @@ typedef struct dd_server_cfg {
     int32_t mode;             /* DD_SERVE_BATCHED, or DD_SERVE_PLAIN: every request runs
                                  alone as a plain execution (the per-request baseline) */
     size_t hbm_budget_bytes;  /* footprint bound and scratch pool size; 0 -> 8 GiB */
-    int32_t max_inflight;     /* slots; 0 -> 2 (batched) or 8 (plain); at most 64 */
+    int32_t max_inflight;     /* slots; 0 -> 6 (batched) or 8 (plain); at most 64 */
     int32_t max_batch;        /* requests per batch; 0 -> 256; at most 4096 (plain: 1) */
     int32_t max_queue;        /* queued, not yet admitted requests; 0 -> 65536 */
     uint32_t flags;           /* DD_TWIDDLE_FP64 or DD_TWIDDLE_FP32, | DD_SERVE_DETERMINISTIC */

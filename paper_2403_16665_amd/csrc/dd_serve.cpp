@@ -147,16 +147,32 @@ void finish(dd_server* s, Req* r, dd_status st, uint64_t t) {
 bool launch_slot(dd_server* s, Slot& slot, std::unique_lock<std::mutex>& lk) {
   const int cap = plain_mode(s) ? 1 : s->cfg.max_batch;
   std::vector<Req*> take;
-  while (!s->pending.empty() && (int)take.size() < cap) {
-    Req* r = s->pending.front();
-    if (s->used + r->footprint > s->cfg.hbm_budget_bytes) break;
+  auto admit = [&](Req* r) {
+    if (s->used + r->footprint > s->cfg.hbm_budget_bytes) return false;
     size_t off = 0;
-    if (r->scratch && !s->ranges.alloc(r->scratch, &off)) break;
+    if (r->scratch && !s->ranges.alloc(r->scratch, &off)) return false;
     r->scratch_off = off;
     s->used += r->footprint;
     s->stats.peak_footprint = std::max(s->stats.peak_footprint, s->used);
-    s->pending.pop_front();
     take.push_back(r);
+    return true;
+  };
+  if (!s->pending.empty() && (plain_mode(s) || !s->pending.front()->kernel)) {
+    // a request outside the batch kernel (large, FP64, or a length the
+    // kernel is not built for) takes a slot of its own, so that its plain
+    // execution overlaps the batches on the other slots' streams
+    if (admit(s->pending.front())) s->pending.pop_front();
+  } else {
+    // a batch gathers the kernel requests in arrival order and steps over
+    // the others, which the next free slot takes; it stops at the first
+    // kernel request that does not fit, so those keep their order
+    int scanned = 0;
+    for (auto it = s->pending.begin(); it != s->pending.end() && (int)take.size() < cap && scanned < 4 * cap;
+         ++scanned) {
+      if (!(*it)->kernel) { ++it; continue; }
+      if (!admit(*it)) break;
+      it = s->pending.erase(it);
+    }
   }
   if (take.empty()) return false;
   slot.busy = true;
@@ -363,7 +379,7 @@ dd_status dense_dft_server_create(const dd_server_cfg* cfg, dd_server_t* out) {
   if (c.flags & ~(uint32_t)(DD_TWIDDLE_FP32 | DD_SERVE_DETERMINISTIC)) return DD_ERR_INVALID;
   if (c.batch_max_bins < -1) return DD_ERR_INVALID;
   if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = (size_t)8 << 30;
-  if (c.max_inflight == 0) c.max_inflight = c.mode == DD_SERVE_PLAIN ? 8 : 2;
+  if (c.max_inflight == 0) c.max_inflight = c.mode == DD_SERVE_PLAIN ? 8 : 6;
   if (c.max_batch == 0) c.max_batch = 256;
   if (c.mode == DD_SERVE_PLAIN) c.max_batch = 1;
   if (c.max_queue == 0) c.max_queue = 65536;
