@@ -66,6 +66,7 @@ def measured_traffic(workload):
 
 WORKLOADS = {
     "batch_c64": dict(batch=256, N=65536, alpha=8, dt=1e-3, input="complex64"),
+    "real_f32": dict(batch=256, N=65536, alpha=8, dt=1e-3, input="float32 real"),
     "precision": dict(batch=1, N=1 << 22, alpha=16, dt=1e-3, input="complex64"),
     "plain_f64": dict(batch=1, N=1024, alpha=4, dt=1e-3, input="float64"),
     "uneven": dict(batch=1000, N=0, alpha=0, dt=1e-3, input="complex64"),
@@ -81,6 +82,8 @@ def make_inputs(name, w):
     N, batch, dt = w["N"], w["batch"], w["dt"]
     if name == "batch_c64":
         return np.stack([siggen.tones_complex(g, N, dt) for g in siggen.rngs(1, batch)])
+    if name == "real_f32":
+        return np.stack([siggen.tones_real(g, N, dt, w["alpha"])[0] for g in siggen.rngs(7, batch)]).astype(np.float32)
     if name == "precision":
         return siggen.precision_tones(siggen.rngs(2, 1)[0], N)[None, :]
     if name == "plain_f64":
@@ -655,6 +658,30 @@ def main():
     }
     if args.workload == "precision":
         result["precision"] = precision_errors(dd, xd, Xd, N, alpha, T)
+    if args.workload == "real_f32":
+        # the same samples through the complex path, which transforms every
+        # scratch row instead of the Hermitian half
+        xc = xd.to(torch.complex64)
+        if args.tune:
+            dd.dense_dft_tune(N, alpha, batch, dd.DD_C64)
+        plan_c = dd.dense_dft_plan(N, alpha, T, batch, dd.DD_C64)
+        Xc = torch.empty_like(Xd)
+        for _ in range(args.warmup):
+            dd.dense_dft_exec(plan_c, xc, Xc, stream=sp)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            dd.dense_dft_exec(plan_c, xc, Xc, stream=sp)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        c_ms = ev0.elapsed_time(ev1) / args.steps
+        worst = 0.0
+        for b in range(0, batch, 51):
+            d = (Xd[b] - Xc[b]).abs().pow(2).sum().sqrt() / Xc[b].abs().pow(2).sum().sqrt()
+            worst = max(worst, float(d))
+        result["complex_path"] = {"ms_per_step": c_ms, "real_path_speedup": c_ms / ms_per_step,
+                                  "max_rel_l2_real_vs_complex": worst,
+                                  "schedule": dd.dense_dft_plan_get_sched(plan_c)}
+        del xc, Xc
     if not args.no_cpu:
         samples, cpu = cpu_baseline(x, alpha, T, M, N)
         got = np.concatenate([Xd[b].cpu().numpy()[bins] for b, bins, _ in samples])

@@ -92,7 +92,9 @@ typedef struct dd_plan *dd_plan_t;
  *   N      : samples per signal: 2^a (a <= 24), 3*2^a (a <= 22) or 5*2^a
  *            (a <= 21), the lengths the kernels are built for (N = N1*N2 with
  *            N1 a power of two, 3 or 5 times one, up to 4096, and N2 a power
- *            of two up to 4096); also alpha*N <= 2^31.
+ *            of two up to 4096); also alpha*N <= 2^31.  In double precision
+ *            a pass-1 column of 4096 does not fit a workgroup's LDS, so N1
+ *            stays below 4096 there and N = 2^24 is unsupported.
  *   alpha  : dense sampling factor, integer >= 1 (alpha < 1 and non-integer
  *            alpha -> DD_ERR_UNSUPPORTED; alpha = 1/p has its own plan,
  *            dense_dft_plan_decimated).

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/dense_dft.h"
@@ -39,10 +40,14 @@ struct dd_plan {
   int s_lines = 1, s_TL = 1;
   size_t s_lds = 0;
   // two passes
-  int p1_lines = 1, p1_TL = 1, p1_ntile = 1, p1_jgroup = 1, p1_njg = 1, p1_pre_lds = 0;
+  int p1_lines = 1, p1_TL = 1, p1_ntile = 1, p1_jgroup = 1, p1_njg = 1, p1_pre_lds = 0, p1_q_lds = 0;
   size_t p1_lds = 0;
   int p2_lines = 1, p2_TL = 1, p2_ntile = 1;
   size_t p2_lds = 0;
+  // real input: pass 1 stores the scratch rows m1 <= alpha N1 / 2 and pass 2
+  // transforms them in blocks of p2_lines + 1 rows (when those fit the LDS)
+  bool p2_half = false;
+  size_t p2h_lds = 0;
   // inverse pass B (every j per block): pre-twiddles staged in LDS, its LDS
   int inv_pre_lds = 0;
   size_t inv_p1_lds = 0;
@@ -123,6 +128,7 @@ bool factor_two_pass(int64_t N, int rbytes, int64_t* N1, int64_t* N2) {
     if (N % n2) continue;
     const int64_t n1 = N / n2;
     if (n1 > 4096 || !len_supported((int)n1) || !pass2_len_supported((int)n2)) continue;
+    if (lds_pass1((int)n1, geom_pass((int)n1, rbytes).lines, rbytes, 0) > (size_t)LDS_PASS_MAX) continue;
     int score = std::abs(ilog2(n1) - ilog2(n2)) * 2 + (n1 > n2 ? 1 : 0);
     if (n2 < 16) score += 8;  // narrow column tiles store short runs
     if (n2 % geom_pass((int)n1, rbytes).lines != 0) score += 4;  // idle columns in pass 1
@@ -203,6 +209,8 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
   p->p2_TL = g2.TL;
   p->p2_ntile = (int)((alpha * N1 + g2.lines - 1) / g2.lines);
   p->p2_lds = lds_pass2((int)N2, g2.lines, p->rbytes);
+  p->p2h_lds = lds_pass2((int)N2, g2.lines, p->rbytes, g2.lines + 1);
+  p->p2_half = (p->dtype == DD_F32 || p->dtype == DD_F64) && p->p2h_lds <= (size_t)LDS_PASS_MAX;
   // signals per pass pair: by default the scratch of one chunk within 128 MiB
   const size_t per_sig = (size_t)M * cx_bytes(p);
   int64_t chunk = sc.chunk;
@@ -225,10 +233,25 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
   p->p1_pre_lds = pre_bytes <= 16 * 1024 &&
                   lds_pass1((int)N1, g1.lines, p->rbytes, jg * (int)N1) <= (size_t)LDS_PASS_MAX ? 1 : 0;
   p->p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, p->p1_pre_lds ? jg * (int)N1 : 0);
+  // and the block's W_{alpha N}^{j n2} when they take at most 4 KiB and do
+  // not cost a block of residency per CU
+  {
+    const int pre_el = p->p1_pre_lds ? jg * (int)N1 : 0;
+    const int q_el = jg * g1.lines;
+    const size_t with_q = lds_pass1((int)N1, g1.lines, p->rbytes, pre_el + q_el);
+    const size_t cu = 160 * 1024;
+    p->p1_q_lds = (size_t)q_el * cx_bytes(p) <= 4096 && with_q <= (size_t)LDS_PASS_MAX &&
+                  cu / with_q == cu / p->p1_lds ? 1 : 0;
+    if (p->p1_q_lds) p->p1_lds = with_q;
+  }
   const size_t inv_pre = (size_t)alpha * N1 * cx_bytes(p);
   p->inv_pre_lds =
       inv_pre <= 16 * 1024 && lds_pass1((int)N1, g1.lines, p->rbytes, alpha * (int)N1) <= (size_t)LDS_PASS_MAX ? 1 : 0;
   p->inv_p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, p->inv_pre_lds ? alpha * (int)N1 : 0);
+  // a column of 4096 doubles with its exchange padding and twiddles exceeds
+  // the LDS of a workgroup
+  if (p->p1_lds > (size_t)LDS_PASS_MAX || p->p2_lds > (size_t)LDS_PASS_MAX || p->inv_p1_lds > (size_t)LDS_PASS_MAX)
+    return DD_ERR_UNSUPPORTED;
   p->ws_bytes = (size_t)chunk * per_sig;
   return DD_OK;
 }
@@ -446,6 +469,17 @@ dd_status dense_dft_sched_candidates(int64_t N, int32_t alpha, int64_t batch, dd
       sc.N2 = n2;
       sc.jgroup = jg;
       add(sc);
+      if (jg == alpha && configure(&p, sc) == DD_OK) {
+        // larger chunks: more pass-1 blocks resident per CU (each block
+        // runs every j of its columns in turn)
+        const int64_t c0 = p.chunk;
+        for (const int64_t ch : {c0 + c0 / 2, 2 * c0}) {
+          if (ch > batch) continue;
+          dd_sched sc2 = sc;
+          sc2.chunk = ch;
+          add(sc2);
+        }
+      }
       if (jg == 1) break;
     }
   }
@@ -505,6 +539,12 @@ dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s
     a1.jgroup = p->p1_jgroup;
     a1.njg = p->p1_njg;
     a1.pre_lds = p->p1_pre_lds;
+    a1.q_lds = p->p1_q_lds;
+    // real samples: the spectrum is Hermitian, so only the scratch rows
+    // m1 <= H = alpha N1 / 2 are stored and transformed (the rest are mirrors)
+    const bool half = std::is_floating_point<In>::value && p->p2_half;
+    const int A = p->alpha * (int)p->N1, H = A / 2;
+    a1.hrows = half ? H + 1 : 0;
     a1.scale = scale;
     a1.twL = static_cast<const cx<R>*>(p->twL1);
     a1.twPre = static_cast<const cx<R>*>(p->twPre);
@@ -515,10 +555,13 @@ dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s
     if (e != hipSuccess) return hip_status(e);
     DenseArgs<R> a2 = a1;
     a2.lines = p->p2_lines;
-    a2.ntile = p->p2_ntile;
+    a2.ntile = half ? (A - H + p->p2_lines - 1) / p->p2_lines : p->p2_ntile;  // blocks of stored rows
     a2.twL = static_cast<const cx<R>*>(p->twL2);
-    LaunchCfg c2{nb * p->p2_ntile, p->p2_lines * p->p2_TL, p->p2_lds, s};
-    e = timed_launch(p, 3, s, [&] { return launch_pass2((int)p->N2, c2, ws, X + c0 * M, a2); });
+    LaunchCfg c2{nb * a2.ntile, (p->p2_lines + (half ? 1 : 0)) * p->p2_TL, half ? p->p2h_lds : p->p2_lds, s};
+    e = timed_launch(p, 3, s, [&] {
+      return half ? launch_pass2_half((int)p->N2, c2, ws, X + c0 * M, a2)
+                  : launch_pass2((int)p->N2, c2, ws, X + c0 * M, a2);
+    });
     if (e != hipSuccess) return hip_status(e);
   }
   return DD_OK;

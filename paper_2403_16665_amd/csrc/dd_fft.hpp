@@ -32,6 +32,8 @@ __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
 }
 template <typename R>
 __device__ __forceinline__ cx<R> cscale(cx<R> a, R s) { return {a.re * s, a.im * s}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cconj(cx<R> a) { return {a.re, -a.im}; }
 // -i * a
 template <typename R>
 __device__ __forceinline__ cx<R> cmul_negi(cx<R> a) { return {a.im, -a.re}; }

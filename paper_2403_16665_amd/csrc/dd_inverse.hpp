@@ -25,11 +25,6 @@
 
 namespace dd {
 
-template <typename R>
-__device__ __forceinline__ cx<R> cconj(cx<R> a) {
-  return {a.re, -a.im};
-}
-
 // One pass: block = `lines` signals.  Their alpha*L spectra are staged in LDS
 // with one contiguous load; for each j, thread t of a line gathers the
 // elements k = t + TL e of the subsequence X_{alpha k + j}.

@@ -22,6 +22,8 @@
 // Every twiddle exponent is an exact integer below its modulus.
 #pragma once
 
+#include <type_traits>
+
 #include "dd_fft.hpp"
 
 namespace dd {
@@ -36,12 +38,26 @@ struct DenseArgs {
   int ntile;          // column tiles (pass 1) or row blocks (pass 2) per signal
   int jgroup, njg;    // j values per block and number of j groups (pass 1)
   int pre_lds;        // pass 1: pre-twiddles of the block's j range staged in LDS
+  int q_lds;          // pass 1: W_{alpha N}^{j n2} of the block's j range and columns staged in LDS
+                      // (a global load inside the j loop would wait for the previous j's stores:
+                      // loads and stores share one in-order counter)
+  int hrows;          // 0: every row m1 of the scratch; real input: floor(alpha N1 / 2) + 1, the rows
+                      // m1 <= alpha N1 / 2 that pass 1 stores and pass 2 transforms (the others are
+                      // conjugate mirrors, X_{alpha N - m} = conj(X_m))
   R scale;            // T / N
   const cx<R>* twL;   // stage twiddles of the line FFT of this kernel ([s][k] per stage)
   const cx<R>* twPre; // W_{alpha N1}^{j n1}, laid out [j][n1]
   const cx<R>* twQ;   // W_{alpha N}^{j n2}, laid out [j][n2]
   const cx<R>* twPost;// W_N^{k1 n2}, laid out [k1][n2]
 };
+
+// A read through an LDS-qualified pointer: keeps the compiler from merging it
+// with a global read of the other branch into one flat load.
+template <typename R>
+__device__ __forceinline__ cx<R> lds_read(const cx<R>* p) {
+  const __attribute__((address_space(3))) R* q = (const __attribute__((address_space(3))) R*)p;
+  return {q[0], q[1]};
+}
 
 template <typename R> __device__ __forceinline__ cx<R> load_in(const float* p, int64_t i) { return {(R)p[i], (R)0}; }
 template <typename R> __device__ __forceinline__ cx<R> load_in(const double* p, int64_t i) { return {(R)p[i], (R)0}; }
@@ -73,10 +89,12 @@ __host__ __device__ constexpr int pass1_lds_elems(int L, int C, int pre) {
   return L * C + (L / 16 + 1) * 8 + line_tw_size(make_line_plan(L)) + pre;
 }
 
-// LDS elements of pass 2 for RB rows: the row exchange buffers, reused as the
+// LDS elements of pass 2 for blocks of RB rows that transform `rows` rows
+// (RB, or RB + 1 for real input): the row exchange buffers, reused as the
 // staging buffer of the transposed store.
-__host__ __device__ constexpr int pass2_lds_elems(int L, int RB) {
-  return RB * (L + L / 16 + 1) > L * (RB + 1) ? RB * (L + L / 16 + 1) : L * (RB + 1);
+__host__ __device__ constexpr int pass2_lds_elems(int L, int RB, int rows = 0) {
+  return (rows ? rows : RB) * (L + L / 16 + 1) > L * (RB + 1) ? (rows ? rows : RB) * (L + L / 16 + 1)
+                                                             : L * (RB + 1);
 }
 
 // LDS of one block of a pass kernel may take all of a CU's 160 KiB: the wider
@@ -224,7 +242,13 @@ __device__ __forceinline__ void body_single_groups(const InAcc& x, cx<R>* __rest
 // group would avoid the block barriers of the exchange but stores 32-byte
 // pieces that reach memory as partial lines: measured 1.8x the write
 // traffic.)
-template <typename R, class InAcc, int L, int C>
+// HALF: the kernel may be given a.hrows > 0 (real input) and then stores
+// only the rows m1 < a.hrows; without it every row is stored.  A real
+// column's alpha-dense DFT is Hermitian, C[alpha N1 - m1] = conj(C[m1]), so
+// C_{alpha-j}[k1] = conj(C_j[N1 - 1 - k1]): when a block holds every j it
+// transforms only j <= alpha / 2 and takes the rows of alpha - j from the
+// transform of j, reversed through LDS.
+template <typename R, class InAcc, int L, int C, bool HALF = false>
 __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y, const DenseArgs<R>& a,
                                            int64_t bid, unsigned char* smem, int tid) {
   constexpr LinePlan P = make_line_plan(L);
@@ -253,26 +277,38 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
     const int n = (j1 - j0) * L;
     for (int i = tid; i < n; i += NT) pre[i] = a.twPre[j0 * L + i];
   }
+  cx<R>* qs = pre + (a.pre_lds ? (j1 - j0) * L : 0);  // [j - j0][c] W_{alpha N}^{j n2} (when a.q_lds)
+  if (a.q_lds) {
+    const int n = (j1 - j0) * C;
+    for (int i = tid; i < n; i += NT) {
+      const int col = tile * C + i % C;
+      qs[i] = col < a.N2 ? a.twQ[(j0 + i / C) * a.N2 + col] : cx<R>{(R)0, (R)0};
+    }
+  }
 
   const bool colok = n2 < N2;  // a tile wider than N2 has idle columns
   cx<R> xv[EPT], pw[EPT];
   const unsigned in_off = (unsigned)(N2 * t + n2);          // lane part of N2 n1 + n2
   const unsigned in_step = (unsigned)(N2 * TL);             // n1 -> n1 + TL
+  // every load of the column in flight at once, then one wait
+  if (colok) {
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    if (colok) {
-      xv[e] = cscale(x(sig * a.x_stride + (int64_t)in_step * e, in_off), a.scale);
-      pw[e] = (a.twPost + in_step * e)[in_off];             // W_N^{k1 n2}, k1 = t + TL e
-    } else {
-      xv[e] = {(R)0, (R)0};
-      pw[e] = {(R)0, (R)0};
-    }
+    for (int e = 0; e < EPT; ++e) xv[e] = x(sig * a.x_stride + (int64_t)in_step * e, in_off);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) pw[e] = (a.twPost + in_step * e)[in_off];  // W_N^{k1 n2}, k1 = t + TL e
+  } else {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) xv[e] = pw[e] = {(R)0, (R)0};
   }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) xv[e] = cscale(xv[e], a.scale);
   __syncthreads();
   const unsigned out_off = (unsigned)(a.alpha * N2 * t + n2);  // lane part of (alpha k1 + j) N2 + n2
   const unsigned out_step = (unsigned)(a.alpha * N2 * TL);
   cx<R>* ys = Y + sig * a.y_stride;
+  const bool sym = HALF && a.hrows > 0 && a.njg == 1;
   for (int j = j0; j < j1; ++j) {
+    if (sym && 2 * j > a.alpha) break;  // stored with their partners alpha - j
     cx<R> v[EPT];
     if (j == 0) {
 #pragma unroll
@@ -288,10 +324,32 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
     }
     line_fft<R, L, false>(v, t, ex, lay, tws);
     if (colok) {
-      const cx<R> q = a.twQ[j * N2 + n2];  // W_{alpha N}^{j n2}
+      const cx<R> q = a.q_lds ? lds_read(qs + (j - j0) * C + c) : a.twQ[j * N2 + n2];  // W_{alpha N}^{j n2}
       cx<R>* yj = ys + (int64_t)j * N2;
+      // rows kept: k1 < (hrows - j) / alpha, i.e. m1 = alpha k1 + j < hrows
+      const int klim = HALF && a.hrows > 0 ? (a.hrows - j + a.alpha - 1) / a.alpha : L;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) (yj + out_step * e)[out_off] = cmul(v[e], cmul(pw[e], q));
+      for (int e = 0; e < EPT; ++e)
+        if (!HALF || t + TL * e < klim) (yj + out_step * e)[out_off] = cmul(v[e], cmul(pw[e], q));
+    }
+    if constexpr (HALF) {
+      if (sym && j >= 1 && 2 * j < a.alpha) {
+        const int jd = a.alpha - j;
+        __syncthreads();  // the transform's last exchange has been read
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) ex[lay(t + TL * e)] = v[e];
+        __syncthreads();
+        if (colok) {
+          const cx<R> q = a.q_lds ? lds_read(qs + (jd - j0) * C + c) : a.twQ[jd * N2 + n2];
+          cx<R>* yj = ys + (int64_t)jd * N2;
+          const int klim = (a.hrows - jd + a.alpha - 1) / a.alpha;
+#pragma unroll
+          for (int e = 0; e < EPT; ++e)
+            if (t + TL * e < klim)
+              (yj + out_step * e)[out_off] = cmul(cconj(ex[lay(L - 1 - t - TL * e)]), cmul(pw[e], q));
+        }
+        __syncthreads();  // before the next transform's exchange
+      }
     }
   }
   __syncthreads();  // LDS tables are rewritten by the next task of a persistent block
@@ -300,9 +358,17 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
 // Pass 2: block = (signal, block of RB consecutive rows m1).  Thread (t, r)
 // with t fastest owns row m1 = block*RB + r, elements n2 = t + TL e.  Output
 // X[m1 + alpha N1 k2] is staged in LDS and written as runs of RB bins.
-template <typename R, int L, int RB>
+// Real input (a.hrows > 0): only rows m1 <= H = floor(alpha N1 / 2) are
+// transformed.  With m = m1 + alpha N1 k2 and 1 <= m1 <= H, the bin
+// alpha N - m = (alpha N1 - m1) + alpha N1 (N2 - 1 - k2) is conj(X_m); rows
+// m1 < alpha N1 - H are stored as they are and rows 1..H also as their
+// conjugate mirrors, which fill rows alpha N1 - H .. alpha N1 - 1 exactly once.
+// With ROWS = RB + 1 a block also transforms the first row of the next block,
+// so that its mirrored rows, (block*RB, block*RB + RB], land on whole runs.
+template <typename R, int L, int RB, int ROWS = RB>
 __device__ __forceinline__ void body_pass2(const cx<R>* __restrict__ Y, cx<R>* __restrict__ X,
                                            const DenseArgs<R>& a, int64_t bid, unsigned char* smem, int tid) {
+  static_assert(ROWS == RB || ROWS == RB + 1, "a block transforms RB or RB + 1 rows");
   constexpr LinePlan P = make_line_plan(L);
   constexpr int EPT = P.EPT;
   constexpr int TL = L / EPT;
@@ -311,8 +377,10 @@ __device__ __forceinline__ void body_pass2(const cx<R>* __restrict__ Y, cx<R>* _
   const int64_t sig = bid / a.ntile;
   const int t = tid % TL, r = tid / TL;
   const int rows = a.alpha * a.N1;
+  const int lim = a.hrows > 0 ? a.hrows : rows;   // rows transformed
+  const int prim = a.hrows > 0 ? rows - (a.hrows - 1) : rows;  // rows stored as they are
   const int m1 = rb * RB + r;
-  const bool ok = m1 < rows;
+  const bool ok = m1 < lim;
   const cx<R>* ys = Y + sig * a.y_stride + (int64_t)rb * RB * L;
   const unsigned row_off = (unsigned)(r * L + t);
   cx<R> v[EPT];
@@ -327,12 +395,21 @@ __device__ __forceinline__ void body_pass2(const cx<R>* __restrict__ Y, cx<R>* _
   __syncthreads();
   cx<R>* xs = X + sig * a.y_stride;
   constexpr int total = RB * L;
-  constexpr int NT = RB * TL;
+  constexpr int NT = ROWS * TL;
 #pragma unroll 4
   for (int i = tid; i < total; i += NT) {
     const int rr = i % RB, k2 = i / RB;
     const int m = rb * RB + rr;
-    if (m < rows) xs[(int64_t)m + (int64_t)rows * k2] = ex[k2 * SR + rr];
+    if (m < prim) xs[(int64_t)m + (int64_t)rows * k2] = ex[k2 * SR + rr];
+  }
+  if (a.hrows > 0) {
+    // conjugate mirrors: consecutive i -> consecutive target rows rows - m
+#pragma unroll 4
+    for (int i = tid; i < total; i += NT) {
+      const int rr = RB - 1 - i % RB + (ROWS - RB), kk = i / RB;
+      const int m = rb * RB + rr;
+      if (m >= 1 && m < lim) xs[(int64_t)(rows - m) + (int64_t)rows * kk] = cconj(ex[(L - 1 - kk) * SR + rr]);
+    }
   }
   __syncthreads();  // the staging buffer is reused by the next task of a persistent block
 }
@@ -364,16 +441,17 @@ __global__ __launch_bounds__(C * (L / make_line_plan(L).EPT)) void k_pass1(const
                                                                           cx<R>* __restrict__ Y,
                                                                           DenseArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  body_pass1<R, PtrIn<R, In>, L, C>(PtrIn<R, In>{x}, Y, a, xcd_contiguous(blockIdx.x, gridDim.x), smem_raw,
+  body_pass1<R, PtrIn<R, In>, L, C, std::is_floating_point<In>::value>(PtrIn<R, In>{x}, Y, a,
+                                                                      xcd_contiguous(blockIdx.x, gridDim.x), smem_raw,
                                     threadIdx.x);
 }
 
-template <typename R, int L, int RB>
-__global__ __launch_bounds__(RB * (L / make_line_plan(L).EPT)) void k_pass2(const cx<R>* __restrict__ Y,
-                                                                           cx<R>* __restrict__ X,
-                                                                           DenseArgs<R> a) {
+template <typename R, int L, int RB, int ROWS>
+__global__ __launch_bounds__(ROWS * (L / make_line_plan(L).EPT)) void k_pass2(const cx<R>* __restrict__ Y,
+                                                                             cx<R>* __restrict__ X,
+                                                                             DenseArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  body_pass2<R, L, RB>(Y, X, a, xcd_contiguous(blockIdx.x, gridDim.x), smem_raw, threadIdx.x);
+  body_pass2<R, L, RB, ROWS>(Y, X, a, xcd_contiguous(blockIdx.x, gridDim.x), smem_raw, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

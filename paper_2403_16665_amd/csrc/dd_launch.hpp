@@ -7,6 +7,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "dd_kernels.hpp"
 
 namespace dd {
@@ -48,6 +51,7 @@ KGeom geom_pass(int L, int rbytes);
   hipError_t launch_pass1(int L, const LaunchCfg& c, const R* x, cx<R>* Y, const DenseArgs<R>& a);      \
   hipError_t launch_pass1(int L, const LaunchCfg& c, const cx<R>* x, cx<R>* Y, const DenseArgs<R>& a);  \
   hipError_t launch_pass2(int L, const LaunchCfg& c, const cx<R>* Y, cx<R>* X, const DenseArgs<R>& a);  \
+  hipError_t launch_pass2_half(int L, const LaunchCfg& c, const cx<R>* Y, cx<R>* X, const DenseArgs<R>& a); \
   hipError_t launch_twiddle(cx<R>* out, int64_t rows, int64_t cols, int64_t r0, int64_t den, int fp32, \
                             hipStream_t s);
 DD_DECL_LAUNCHERS(float)
@@ -76,8 +80,17 @@ inline size_t lds_single(int L, int lines, int alpha, int rbytes) {
 inline size_t lds_pass1(int L, int lines, int rbytes, int pre_elems) {
   return (size_t)pass1_lds_elems(L, lines, pre_elems) * 2 * rbytes;
 }
-inline size_t lds_pass2(int L, int lines, int rbytes) {
-  return (size_t)pass2_lds_elems(L, lines) * 2 * rbytes;
+inline size_t lds_pass2(int L, int lines, int rbytes, int rows = 0) {
+  return (size_t)pass2_lds_elems(L, lines, rows) * 2 * rbytes;
+}
+
+// With DD_DEBUG set in the environment, a failed launch is reported on
+// stderr with its geometry.
+inline hipError_t report_launch(hipError_t e, const char* what, const LaunchCfg& c) {
+  if (e != hipSuccess && std::getenv("DD_DEBUG"))
+    std::fprintf(stderr, "dense_dft: %s failed: %s (grid %lld, block %d, LDS %zu bytes)\n", what,
+                 hipGetErrorString(e), (long long)c.grid, c.block, c.lds);
+  return e;
 }
 
 // Kernel launch with the dynamic-LDS attribute raised when needed.
@@ -86,11 +99,14 @@ inline hipError_t launch_kernel(K kern, const LaunchCfg& c, Args... args) {
   if (c.lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+      (void)hipGetLastError();  // do not leave the error for the next launch to report
+      return report_launch(e, "raising the LDS limit", c);
+    }
   }
   if (c.grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(kern, dim3((unsigned)c.grid), dim3(c.block), c.lds, c.stream, args...);
-  return hipGetLastError();
+  return report_launch(hipGetLastError(), "kernel launch", c);
 }
 
 }  // namespace dd

@@ -11,4 +11,8 @@ hipError_t launch_pass1(int L, const LaunchCfg& c, const cx<float>* x, cx<float>
 hipError_t launch_pass2(int L, const LaunchCfg& c, const cx<float>* Y, cx<float>* X, const DenseArgs<float>& a) {
   return launch_pass2_impl<float>(L, c, Y, X, a);
 }
+hipError_t launch_pass2_half(int L, const LaunchCfg& c, const cx<float>* Y, cx<float>* X,
+                             const DenseArgs<float>& a) {
+  return launch_pass2_impl<float, true>(L, c, Y, X, a);
+}
 }  // namespace dd

@@ -11,4 +11,8 @@ hipError_t launch_pass1(int L, const LaunchCfg& c, const cx<double>* x, cx<doubl
 hipError_t launch_pass2(int L, const LaunchCfg& c, const cx<double>* Y, cx<double>* X, const DenseArgs<double>& a) {
   return launch_pass2_impl<double>(L, c, Y, X, a);
 }
+hipError_t launch_pass2_half(int L, const LaunchCfg& c, const cx<double>* Y, cx<double>* X,
+                             const DenseArgs<double>& a) {
+  return launch_pass2_impl<double, true>(L, c, Y, X, a);
+}
 }  // namespace dd

@@ -50,6 +50,8 @@ def test_binding_loads_and_names_match():
     (7, 2, 1.0, 1, 1, 0, 2),                 # prime factor > 5
     (15 * 4096, 2, 1.0, 1, 1, 0, 2),         # 3 and 5 in one length: not a built length
     (1 << 25, 2, 1.0, 1, 1, 0, 2),           # beyond 4096 x 4096
+    (1 << 24, 2, 1.0, 1, 2, 0, 2),           # double: 4096 x 4096 needs a column of 4096 in LDS
+    (1 << 24, 2, 1.0, 1, 3, 0, 2),
     (1 << 20, 4096, 1.0, 1, 1, 0, 2),        # alpha*N > 2^31
 ])
 def test_plan_rejects_bad_arguments(N, alpha, T, batch, dtype, flags, want):
@@ -59,6 +61,23 @@ def test_plan_rejects_bad_arguments(N, alpha, T, batch, dtype, flags, want):
     rc = dd._lib.dense_dft_plan(ctypes.byref(h), N, alpha, T, batch, dtype, flags)
     assert rc == want
     assert not h.value  # out-param cleared on failure
+
+
+@pytest.mark.parametrize("dtype,n1_4096", [(0, True), (1, True), (2, False), (3, False)])
+def test_schedules_fit_workgroup_lds(dtype, n1_4096):
+    """A pass-1 column of 4096 fits a workgroup's LDS in single precision
+    only: in double the planner neither offers nor accepts that schedule."""
+    import ctypes
+    import paper_2403_16665_amd as dd
+    two = [sc for sc in dd.dense_dft_sched_candidates(8192, 2, 3, dtype) if sc.passes == 2]
+    assert two
+    assert any(sc.N1 == 4096 for sc in two) == n1_4096
+    if not n1_4096:
+        h = ctypes.c_void_p(12345)
+        sc = dd.make_sched(2, N1=4096, N2=2)
+        rc = dd._lib.dense_dft_plan_sched(ctypes.byref(h), 8192, 2, 1.0, 3, dtype, dd.DD_TWIDDLE_FP64,
+                                          ctypes.byref(sc))
+        assert rc == 2 and not h.value
 
 
 def test_null_handles_rejected():
