@@ -185,6 +185,12 @@ inline void fill_item(BatchItem& it, const dd_desc& d, const ClassTables& ct, cx
     it.jgroup = d.alpha;
     it.njg = 1;
     it.pre_lds = (size_t)d.alpha * sc.N1 * 8 <= 16 * 1024 ? 1 : 0;
+    // the j loop then reads no global memory, so it does not wait for the
+    // stores of the previous j
+    it.q_lds = 0;
+    const size_t with_q =
+        (size_t)pass1_lds_elems(sc.N1, C, (it.pre_lds ? d.alpha * sc.N1 : 0) + d.alpha * C) * 8;
+    if ((size_t)d.alpha * C * 8 <= 4096 && with_q <= (size_t)BATCH_LDS_MAX) it.q_lds = 1;
     it.ntile2 = (d.alpha * sc.N1 + RB - 1) / RB;
     it.p1_tasks = it.ntile1 * it.njg;
     it.code1 = batch_code(BK_PASS1, sc.N1);
@@ -196,7 +202,8 @@ inline void fill_item(BatchItem& it, const dd_desc& d, const ClassTables& ct, cx
 // the second (pass-2) queue kernel.
 inline size_t item_lds1(const BatchItem& it) {
   if (it.code2 < 0) return batch_single_lds(it.N1, it.alpha, it.lines1);
-  return (size_t)pass1_lds_elems(it.N1, batch_lines(it.N1), it.pre_lds ? it.alpha * it.N1 : 0) * 8;
+  const int C = batch_lines(it.N1);
+  return (size_t)pass1_lds_elems(it.N1, C, (it.pre_lds ? it.alpha * it.N1 : 0) + (it.q_lds ? it.alpha * C : 0)) * 8;
 }
 inline size_t item_lds2(const BatchItem& it) { return it.code2 < 0 ? 0 : lds_pass2(it.N2, batch_lines(it.N2), 4); }
 
