@@ -71,6 +71,7 @@ template <typename R, typename In>
 struct PtrIn {
   const In* p;
   __device__ __forceinline__ cx<R> operator()(int64_t base, unsigned off) const { return load_in<R>(p + base, off); }
+  __device__ __forceinline__ bool is_real() const { return std::is_floating_point<In>::value; }
 };
 // Runtime choice between real float and complex float samples (mixed batches).
 template <typename R>
@@ -81,6 +82,7 @@ struct AnyIn {
     return real ? load_in<R>(static_cast<const float*>(p) + base, off)
                 : load_in<R>(static_cast<const cx<float>*>(p) + base, off);
   }
+  __device__ __forceinline__ bool is_real() const { return real != 0; }
 };
 
 // LDS elements of pass 1 for a tile of C columns (host and device): the
@@ -157,7 +159,12 @@ __device__ __forceinline__ void body_single(const InAcc& x, cx<R>* __restrict__ 
     xv[e] = active ? cscale(x(sig * a.x_stride, (unsigned)(t + TL * e)), a.scale) : cx<R>{(R)0, (R)0};
   const RowLayout<L> lay(act ? line : 0);
   cx<R>* im = img + (int64_t)line * M1;
-  for (int j = 0; j < a.alpha; ++j) {
+  // real samples: X_{alpha L - m} = conj(X_m), so with m = alpha k + j the
+  // bins of alpha - j are conj(X_{alpha (L - 1 - k) + j}); only j <= alpha/2
+  // are transformed, and each j in [1, alpha/2) also fills its mirror
+  const bool herm = x.is_real();
+  const int jmax = herm ? a.alpha / 2 : a.alpha - 1;
+  for (int j = 0; j <= jmax; ++j) {
     cx<R> v[EPT];
     if (j == 0) {
 #pragma unroll
@@ -171,6 +178,10 @@ __device__ __forceinline__ void body_single(const InAcc& x, cx<R>* __restrict__ 
     if (act) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) im[a.alpha * (t + TL * e) + j] = v[e];
+      if (herm && j >= 1 && 2 * j < a.alpha) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) im[a.alpha * (L - 1 - t - TL * e) + a.alpha - j] = cconj(v[e]);
+      }
     }
   }
   __syncthreads();
@@ -208,9 +219,12 @@ __device__ __forceinline__ void body_single_groups(const InAcc& x, cx<R>* __rest
   for (int e = 0; e < EPT; ++e)
     xv[e] = member ? cscale(x(sig * a.x_stride, (unsigned)(t + TL * e)), a.scale) : cx<R>{(R)0, (R)0};
   const RowLayout<L> lay(member ? g : 0);
-  for (int j0 = 0; j0 < a.alpha; j0 += groups) {  // uniform over the block
+  // real samples: only j <= alpha/2 are transformed (as in body_single)
+  const bool herm = x.is_real();
+  const int jmax = herm ? a.alpha / 2 : a.alpha - 1;
+  for (int j0 = 0; j0 <= jmax; j0 += groups) {  // uniform over the block
     const int j = j0 + g;
-    const bool act = member && j < a.alpha;
+    const bool act = member && j <= jmax;
     cx<R> v[EPT];
     if (j == 0 || !act) {
 #pragma unroll
@@ -224,6 +238,10 @@ __device__ __forceinline__ void body_single_groups(const InAcc& x, cx<R>* __rest
     if (act) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) img[a.alpha * (t + TL * e) + j] = v[e];
+      if (herm && j >= 1 && 2 * j < a.alpha) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) img[a.alpha * (L - 1 - t - TL * e) + a.alpha - j] = cconj(v[e]);
+      }
     }
   }
   __syncthreads();

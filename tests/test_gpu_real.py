@@ -69,6 +69,37 @@ def test_real_every_two_pass_schedule_every_bin(oracle_mod, N, alpha, dtype, kin
             check_mirror(X[b], M, alpha * N1, what)
 
 
+SINGLE_N = [1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192,
+            256, 320, 384, 512, 640, 768, 1024, 1280, 1536, 2048, 2560, 3072, 4096]
+
+
+@pytest.mark.parametrize("N", SINGLE_N)
+@pytest.mark.parametrize("dtype,kind", [(np.float32, "f32"), (np.float64, "f64")])
+def test_real_one_pass_every_bin(oracle_mod, N, dtype, kind):
+    """One-pass transforms of real signals transform only j <= alpha/2 and
+    write the bins alpha (N - 1 - k) + alpha - j as conjugates of
+    alpha k + j: every bin against the oracle, and those bins exact."""
+    import torch
+    import paper_2403_16665_amd as dd
+    code = dd.DD_F32 if dtype == np.float32 else dd.DD_F64
+    for alpha in (1, 2, 3, 5, 8, 16):
+        rng = np.random.default_rng(17 * N + alpha)
+        x = rng.standard_normal((3, N)).astype(dtype)
+        T = 0.5
+        plan = dd.dense_dft_plan(N, alpha, T, 3, code)
+        if dd.dense_dft_plan_info(plan)[0] != 1:
+            continue  # alpha N too large for one pass in this precision
+        X = dd.alpha_dft(torch.from_numpy(x).cuda(), alpha, T, plan=plan).cpu().numpy()
+        M = alpha * N
+        m = np.arange(M)
+        j = m % alpha
+        mirrored = m[(j >= 1) & (2 * j > alpha)]
+        for b in range(3):
+            what = f"real {dtype.__name__} one pass N={N} alpha={alpha} signal {b}"
+            assert_close(X[b], oracle_mod.alpha_dft(x[b], alpha, T), kind, what)
+            assert np.array_equal(X[b][mirrored], np.conj(X[b][M - mirrored])), what
+
+
 def test_real_matches_complex_path_default_shape(oracle_mod):
     """256 x 65536 real float32 at alpha = 8 (the default workload's shape):
     the real path and the complex path on the same samples agree over the
