@@ -28,6 +28,9 @@
  *   - Input dtypes: DD_F32 (real float), DD_C64 (complex float),
  *     DD_F64 (real double), DD_C128 (complex double).  The output is
  *     complex64 for DD_F32 / DD_C64 and complex128 for DD_F64 / DD_C128.
+ *     Real input still yields all alpha*N bins; the kernels compute about
+ *     half of them and write the rest as conjugates, X_{alpha N - m} =
+ *     conj(X_m), which then hold exactly.
  *   - Execution calls only enqueue work on the given HIP stream (NULL = the
  *     default stream) and return at once; device faults surface at the
  *     caller's synchronisation or as DD_ERR_DEVICE from a later call.
