@@ -80,6 +80,18 @@ def test_schedules_fit_workgroup_lds(dtype, n1_4096):
         assert rc == 2 and not h.value
 
 
+def test_chunk_candidates():
+    """Two-pass candidates with every j per block also come with 1.5x and 2x
+    the default chunk (32 signals of 4 MiB scratch here), within the batch."""
+    import paper_2403_16665_amd as dd
+    chunks = {sc.chunk for sc in dd.dense_dft_sched_candidates(65536, 8, 256, 1)
+              if sc.passes == 2 and sc.N1 == 256 and sc.jgroup == 8}
+    assert chunks == {32, 48, 64}
+    chunks = {sc.chunk for sc in dd.dense_dft_sched_candidates(65536, 8, 40, 1)
+              if sc.passes == 2 and sc.N1 == 256 and sc.jgroup == 8}
+    assert chunks == {32}
+
+
 def test_null_handles_rejected():
     import ctypes
     import paper_2403_16665_amd as dd
