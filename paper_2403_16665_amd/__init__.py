@@ -160,7 +160,28 @@ class Plan:
 
     @property
     def M(self) -> int:
-        return self.alpha * self.N
+        """Bins per signal: alpha*N, or N/p for an alpha = 1/p plan."""
+        p = getattr(self, "p", 0)
+        return self.N // p if p else self.alpha * self.N
+
+    def exec(self, x, out=None, stream=None, workspace=None):
+        """Enqueue the transform of device tensor x ([batch, N] of the plan's
+        dtype) into ``out`` ([batch, M] complex; allocated when None) on
+        ``stream`` (default: torch's current stream); returns ``out``."""
+        if out is None:
+            import torch
+            out = torch.empty((self.batch, self.M), dtype=out_dtype(self.dtype), device=x.device)
+        dense_dft_exec(self, x, out, workspace, stream)
+        return out
+
+    def exec_inverse(self, X, out=None, stream=None, workspace=None):
+        """Enqueue the inverse transform of device spectra X ([batch, alpha*N])
+        into ``out`` ([batch, N] complex; allocated when None); returns ``out``."""
+        if out is None:
+            import torch
+            out = torch.empty((self.batch, self.N), dtype=out_dtype(self.dtype), device=X.device)
+        dense_dft_exec_inverse(self, X, out, workspace, stream)
+        return out
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -175,6 +196,13 @@ def dense_dft_plan(N: int, alpha: int, T: float, batch: int, dtype: int,
     _check(_lib.dense_dft_plan(ctypes.byref(h), int(N), int(alpha), float(T), int(batch),
                                int(dtype), int(flags)), "dense_dft_plan")
     return Plan(h, int(N), int(alpha), float(T), int(batch), int(dtype), int(flags))
+
+
+def plan(N: int, alpha: int, T: float, batch: int, dtype, flags: int = DD_TWIDDLE_FP64) -> Plan:
+    """dense_dft_plan with ``dtype`` a DD_* code or a torch dtype
+    (float32, complex64, float64, complex128)."""
+    code = dtype if isinstance(dtype, int) else dtype_code(dtype)
+    return dense_dft_plan(N, alpha, T, batch, code, flags)
 
 
 def dense_dft_workspace_size(plan: Plan) -> int:
