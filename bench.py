@@ -136,6 +136,16 @@ def precision_errors(dd, xd, Xd, N, alpha, T):
     return out
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(x_rows, alpha, T, M, N, target_s=20.0):
     """Time the FP64 oracle on a bounded sample of the workload (host cores):
     all bins of signal 0, then of signal 1, ..., or a seeded subset of the
@@ -162,7 +172,8 @@ def cpu_baseline(x_rows, alpha, T, M, N, target_s=20.0):
         samples.append((b, bins, ref))
         done += len(bins)
     nsig = len(samples)
-    return samples, {"value": done / el, "unit": "bins/s", "cores": oracle.threads(), "kind": "oracle",
+    return samples, {"value": done / el, "unit": "bins/s", "cores": oracle.threads(), "cpu_model": cpu_model(),
+                     "kind": "oracle",
                      "sample": f"{done} seeded bins of the first {nsig} signal(s) (each bin = {N} complex "
                                f"multiply-adds, FP64 direct sum), {el:.1f} s"}
 
@@ -614,6 +625,29 @@ def main():
     gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = gpu_ms / args.steps
 
+    # per-step device times (p50 / p99): the same K steps, one event pair each
+    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+    for e0, e1 in step_ev:
+        e0.record(stream)
+        dd.dense_dft_exec(plan, xd, Xd, stream=sp)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    step_ms = np.array([e0.elapsed_time(e1) for e0, e1 in step_ev])
+
+    # the copy ceiling on this device: a plain 1 GiB device-to-device copy
+    cbuf = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    cdst = torch.empty_like(cbuf)
+    cdst.copy_(cbuf)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(3):
+        cdst.copy_(cbuf)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 3 * 2 * (1 << 30) / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del cbuf, cdst
+
     # per-kernel durations: the same K steps with every launch bracketed by events
     dd.dense_dft_profile_begin(plan, 1 << 16)
     for _ in range(args.steps):
@@ -650,12 +684,17 @@ def main():
                    "schedule": dd.dense_dft_plan_get_sched(plan)},
         "tuning": tuning,
         "hbm_frac_end_to_end": b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "step_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
+        "copy_ceiling_GBps": copy_gbs,
         "kernels": kernels,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "what": "whole transform per step (all its kernels): algorithmic bytes "
                              "batch*(N*s_in + alpha*N*s_out) / summed kernel durations"},
     }
+    traffic = result["roofline"]["traffic"]
+    if traffic:
+        result["roofline"]["amplification"] = traffic / b_alg   # measured HBM bytes / algorithmic
     if args.workload == "precision":
         result["precision"] = precision_errors(dd, xd, Xd, N, alpha, T)
     if args.workload == "real_f32":
