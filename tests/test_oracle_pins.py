@@ -227,6 +227,42 @@ def test_large_M_direct_sincos_path(oracle_mod):
     assert rel(got, ref) < 1e-11
 
 
+# --- the oracle's own rounding, against extended precision ---
+def longdouble_bins(x, alpha, T, bins):
+    """The definition summed in x86 80-bit long double: exponents reduced
+    exactly in integers, cos/sin of the long-double angle."""
+    N = len(x)
+    M = alpha * N
+    ld = np.longdouble
+    xr = np.asarray(x.real, dtype=ld)
+    xi = np.asarray(x.imag, dtype=ld)
+    n = np.arange(N, dtype=np.int64)
+    two_pi = ld(2) * np.arccos(ld(-1))
+    out = []
+    for m in bins:
+        q = (int(m) * n) % M
+        th = two_pi * q.astype(ld) / ld(M)
+        c, s = np.cos(th), np.sin(th)
+        re = np.sum(xr * c + xi * s)
+        im = np.sum(xi * c - xr * s)
+        out.append(complex(float(re * ld(T) / ld(N)), float(im * ld(T) / ld(N))))
+    return np.array(out)
+
+
+@pytest.mark.skipif(np.finfo(np.longdouble).eps > 1e-18, reason="long double is not 80-bit here")
+@pytest.mark.parametrize("N,alpha", [(4096, 8), (4096, 1 << 14)])
+def test_oracle_rounding_against_long_double(oracle_mod, N, alpha):
+    """Random bins of a random signal, at a small M and at M = 2^26 (the
+    large-M twiddle path): the FP64 oracle is within 1e-13 of the sum in
+    extended precision."""
+    rng = np.random.default_rng(21)
+    x = rand_c(rng, N)
+    bins = siggen.bin_subset(rng, alpha * N, 64)
+    got = oracle_mod.alpha_dft_bins(x, alpha, 0.75, bins)
+    ref = longdouble_bins(x, alpha, 0.75, bins)
+    assert rel(got, ref) < 1e-13
+
+
 # --- planted mistakes must be caught ---
 def _pins_pass(oracle_mod, mutation):
     rng = np.random.default_rng(99)
