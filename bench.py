@@ -546,6 +546,9 @@ def main():
     ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000,100000,200000,400000,800000",
                     help="serving: Poisson arrival rates (requests/s)")
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests per rate")
+    ap.add_argument("--tune-db", default="", metavar="PATH",
+                    help="default-shape workloads: load the tuning table from PATH if it exists, "
+                         "else tune and save it there (profiling runs then time the same schedule)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="instead of the transform, run --steps plain device copies of MIB MiB "
                          "(calibrates the profiler's HBM byte counters)")
@@ -599,10 +602,16 @@ def main():
     xd = torch.from_numpy(x).to(dev)
     code = dd.dtype_code(xd.dtype)
     tuning = None
-    if args.tune:
+    if args.tune_db and os.path.exists(args.tune_db):
+        # a table saved by an earlier run: the same schedules, no tuner launches
+        dd.dense_dft_tune_load(args.tune_db)
+        tuning = {"loaded": args.tune_db}
+    elif args.tune:
         t_tune = time.perf_counter()
         tuning = dd.dense_dft_tune(N, alpha, batch, code)
         tuning["seconds"] = time.perf_counter() - t_tune
+        if args.tune_db:
+            dd.dense_dft_tune_save(args.tune_db)
     plan = dd.dense_dft_plan(N, alpha, T, batch, code)
     Xd = torch.empty((batch, M), dtype=dd.out_dtype(code), device=dev)
     stream = torch.cuda.Stream(device=dev)
