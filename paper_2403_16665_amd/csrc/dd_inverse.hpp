@@ -45,7 +45,7 @@ __device__ __forceinline__ void body_single_inv(const cx<R>* __restrict__ X, cx<
   const int M1 = a.alpha * L;
   const int64_t nl = min((int64_t)a.lines, a.batch - sig0);
   const cx<R>* src = X + sig0 * a.y_stride;  // y_stride == alpha * L
-  for (int64_t i = tid; i < nl * M1; i += nt) img[i] = src[i];
+  for (int64_t i = tid; i < nl * M1; i += nt) img[i] = load_once(src + i);
   __syncthreads();
   const RowLayout<L> lay(act ? line : 0);
   const cx<R>* im = img + (int64_t)(active ? line : 0) * M1;
@@ -69,7 +69,7 @@ __device__ __forceinline__ void body_single_inv(const cx<R>* __restrict__ X, cx<
   if (active) {
     cx<R>* xs = x + sig * a.x_stride;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) xs[t + TL * e] = cscale(cconj(acc[e]), a.scale);
+    for (int e = 0; e < EPT; ++e) store_out(xs + t + TL * e, cscale(cconj(acc[e]), a.scale));
   }
 }
 
@@ -104,7 +104,7 @@ __device__ __forceinline__ void body_passA(const cx<R>* __restrict__ X, cx<R>* _
   cx<R> g[EPT];
 #pragma unroll
   for (int u = 0; u < EPT; ++u)
-    g[u] = mrow < rows ? xs[(int64_t)mrow + (int64_t)rows * (kb + u * TL)] : cx<R>{(R)0, (R)0};
+    g[u] = mrow < rows ? load_once(xs + (int64_t)mrow + (int64_t)rows * (kb + u * TL)) : cx<R>{(R)0, (R)0};
 #pragma unroll
   for (int u = 0; u < EPT; ++u) ex[(kb + u * TL) * SR + rr] = g[u];
   __syncthreads();
@@ -120,8 +120,16 @@ __device__ __forceinline__ void body_passA(const cx<R>* __restrict__ X, cx<R>* _
     const cx<R>* __restrict__ pw = a.twPost + (int64_t)k1 * L + t;
     const cx<R>* __restrict__ q = a.twQ + (int64_t)j * L + t;
     cx<R>* gr = G + sig * a.y_stride + (int64_t)m1 * L + t;
+    // every twiddle load before the first store: loads and stores share one
+    // in-order completion counter, so a load issued after a store would wait
+    // for that store too
+    cx<R> w[EPT];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) gr[TL * e] = cmul(v[e], cmul(pw[TL * e], q[TL * e]));
+    for (int e = 0; e < EPT; ++e) w[e] = pw[TL * e];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) w[e] = cmul(w[e], q[TL * e]);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) gr[TL * e] = cmul(v[e], w[e]);
   }
 }
 
@@ -182,7 +190,7 @@ __device__ __forceinline__ void body_passB(const cx<R>* __restrict__ G, cx<R>* _
     const unsigned out_step = (unsigned)(N2 * TL);
     const unsigned out_off = (unsigned)(N2 * t);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) (xs + out_step * e)[out_off] = cscale(cconj(acc[e]), a.scale);
+    for (int e = 0; e < EPT; ++e) store_out(xs + out_step * e + out_off, cscale(cconj(acc[e]), a.scale));
   }
 }
 

@@ -70,6 +70,15 @@ __device__ __forceinline__ void store_out(cx<R>* p, cx<R> v) {
   __builtin_nontemporal_store(v.im, q + 1);
 }
 
+// Load of a value read once (the spectra the inverse transform consumes),
+// marked non-temporal for the same reason (the inverse of the default shape:
+// 0.811 -> 0.768 ms, pass B finding more of its scratch in the cache).
+template <typename R>
+__device__ __forceinline__ cx<R> load_once(const cx<R>* p) {
+  const R* q = reinterpret_cast<const R*>(p);
+  return {__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1)};
+}
+
 template <typename R> __device__ __forceinline__ cx<R> load_in(const float* p, int64_t i) { return {(R)p[i], (R)0}; }
 template <typename R> __device__ __forceinline__ cx<R> load_in(const double* p, int64_t i) { return {(R)p[i], (R)0}; }
 template <typename R> __device__ __forceinline__ cx<R> load_in(const cx<float>* p, int64_t i) { cx<float> v = p[i]; return {(R)v.re, (R)v.im}; }
