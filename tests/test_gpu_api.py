@@ -1,0 +1,85 @@
+"""Entry points around the transform: per-launch profiling of a plan and the
+server's open-loop submission of a pre-drawn arrival schedule."""
+import numpy as np
+import pytest
+
+import siggen
+from parity import assert_close, spectrum_rms
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_profile_records_every_launch():
+    """Two passes over two chunks, then the inverse: one record per kernel
+    launch in enqueue order, each with a positive duration; a one-pass plan
+    records kind `single`; max_launches bounds what is recorded."""
+    import torch
+    import paper_2403_16665_amd as dd
+    N, alpha, batch = 65536, 8, 35
+    sc = dd.make_sched(2, N1=256, N2=256, jgroup=8, chunk=32)
+    plan = dd.dense_dft_plan_sched(N, alpha, 1.0, batch, dd.DD_C64, sc)
+    x = torch.randn(batch, N, dtype=torch.complex64, device="cuda")
+    X = torch.empty(batch, alpha * N, dtype=torch.complex64, device="cuda")
+    back = torch.empty_like(x)
+    dd.dense_dft_profile_begin(plan, 64)
+    dd.dense_dft_exec(plan, x, X)
+    dd.dense_dft_exec_inverse(plan, X, back)
+    rec = dd.dense_dft_profile_end(plan)
+    assert [k for k, _ in rec] == ["pass1", "pass2", "pass1", "pass2",
+                                   "inverse_passA", "inverse_passB", "inverse_passA", "inverse_passB"]
+    assert all(ms > 0 for _, ms in rec)
+    # profiling is off again: a further execution records nothing
+    dd.dense_dft_exec(plan, x, X)
+    dd.dense_dft_profile_begin(plan, 1)
+    dd.dense_dft_exec(plan, x, X)
+    assert [k for k, _ in dd.dense_dft_profile_end(plan)] == ["pass1"]
+    one = dd.dense_dft_plan(1024, 4, 1.0, 3, dd.DD_F32)
+    xr = torch.randn(3, 1024, device="cuda")
+    dd.dense_dft_profile_begin(one, 8)
+    dd.dense_dft_exec(one, xr, torch.empty(3, 4096, dtype=torch.complex64, device="cuda"))
+    rec = dd.dense_dft_profile_end(one)
+    assert [k for k, _ in rec] == ["single"] and rec[0][1] > 0
+
+
+def test_submit_many_at_open_loop(oracle_mod):
+    """Requests queued at pre-drawn host times: each is stamped with its
+    scheduled arrival, starts no earlier and finishes after it starts, and
+    its spectrum matches the oracle.  Non-decreasing times are required."""
+    import torch
+    import paper_2403_16665_amd as dd
+    rng = np.random.default_rng(12)
+    shapes = [(1024, 4), (4096, 8), (65536, 2), (3 * 2 ** 10, 3), (262144, 16), (256, 16)]
+    xs, Xs, descs = [], [], []
+    for i, (N, a) in enumerate(shapes):
+        x = (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64) if i % 2 else \
+            rng.standard_normal(N).astype(np.float32)
+        xs.append(torch.from_numpy(x).cuda())
+        Xs.append(torch.zeros(a * N, dtype=torch.complex64, device="cuda"))
+        descs.append((N, a, N * 1e-3, dd.DD_C64 if i % 2 else dd.DD_F32, xs[-1], Xs[-1]))
+    torch.cuda.synchronize()
+    srv = dd.dense_dft_server_create(hbm_budget_bytes=1 << 30)
+    t0 = dd.dense_dft_clock_ns() + 1_000_000
+    due = [t0 + i * 200_000 for i in range(len(descs))]
+    tickets = dd.dense_dft_submit_many_at(srv, descs, due)
+    res = [dd.dense_dft_wait(srv, t, 30_000_000) for t in tickets]
+    for r, d in zip(res, due):
+        assert r["status"] == 0
+        assert r["t_arrival_ns"] == d and r["t_start_ns"] >= d and r["t_done_ns"] >= r["t_start_ns"]
+    for (N, a), x, X in zip(shapes, xs, Xs):
+        xn = x.cpu().numpy()
+        bins = siggen.bin_subset(rng, a * N, 256)
+        full = None if len(bins) == a * N else spectrum_rms(xn, N * 1e-3)
+        assert_close(X.cpu().numpy()[bins], oracle_mod.alpha_dft_bins(xn, a, N * 1e-3, bins), "f32",
+                     f"N={N} alpha={a}", full_rms=full)
+    # a decreasing time is refused at that request; the ones before it are queued
+    now = dd.dense_dft_clock_ns()
+    with pytest.raises(dd.DenseDFTError, match="queued 1 of 2"):
+        dd.dense_dft_submit_many_at(srv, descs[:2], [now + 100_000, now])
+    dd.dense_dft_server_destroy(srv)   # drains the queued request
