@@ -110,8 +110,9 @@ void free_tables(dd_plan* p) {
   }
 }
 
-dd_status gen_stage_table(dd_plan* p, void** out, int L, bool fp32, hipStream_t s) {
-  return make_stage_table(out, L, p->dbl, fp32, s);
+// narrow: the table of a one-pass plan's line (the one-pass kernels' plan)
+dd_status gen_stage_table(dd_plan* p, void** out, int L, bool fp32, hipStream_t s, bool narrow = false) {
+  return make_stage_table(out, L, p->dbl, fp32, s, narrow);
 }
 
 dd_status gen_table(dd_plan* p, void** out, int64_t rows, int64_t cols, int64_t den, bool fp32,
@@ -314,7 +315,7 @@ dd_status plan_build(dd_plan_t* out, int64_t N, int32_t alpha, double T, int64_t
 
   // Device tables, generated on the GPU (FP64 unless the FP32 variant).
   hipStream_t s = nullptr;
-  st = gen_stage_table(p, &p->twL1, (int)p->N1, fp32tw, s);
+  st = gen_stage_table(p, &p->twL1, (int)p->N1, fp32tw, s, p->passes == 1 && single_narrow((int)p->N1));
   if (st == DD_OK) st = gen_table(p, &p->twPre, alpha, p->N1, (int64_t)alpha * p->N1, fp32tw, s);
   if (st == DD_OK && p->passes == 2) {
     st = gen_stage_table(p, &p->twL2, (int)p->N2, fp32tw, s);

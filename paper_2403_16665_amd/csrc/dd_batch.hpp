@@ -56,7 +56,7 @@ __host__ __device__ inline int batch_single_groups(int L, int alpha) {
   switch (L) {
 #define DD_SG(LL)                                                                                        \
   case LL: {                                                                                             \
-    int g = BATCH_THREADS / line_threads(LL);                                                            \
+    int g = BATCH_THREADS / single_line_threads(LL);                                                     \
     while (g > 1 && (g / 2 >= alpha || (size_t)single_groups_lds_elems<LL>(g, alpha) * 8 > (size_t)BATCH_LDS_MAX)) \
       g /= 2;                                                                                            \
     return (size_t)single_groups_lds_elems<LL>(g, alpha) * 8 <= (size_t)BATCH_LDS_MAX ? g : 0;          \

@@ -144,7 +144,7 @@ inline dd_status make_class_tables(int64_t N, int alpha, const Sched& sc, bool f
                                    ClassTables* ct) {
   ct->sc = sc;
   const int64_t M = (int64_t)alpha * N;
-  dd_status st = make_stage_table(&ct->twL1, sc.N1, false, fp32tw, s);
+  dd_status st = make_stage_table(&ct->twL1, sc.N1, false, fp32tw, s, sc.single && single_narrow(sc.N1));
   if (st == DD_OK) st = make_table(&ct->twPre, alpha, sc.N1, (int64_t)alpha * sc.N1, false, fp32tw, s);
   if (st == DD_OK && !sc.single) {
     st = make_table(&ct->twQ, alpha, sc.N2, M, false, fp32tw, s);

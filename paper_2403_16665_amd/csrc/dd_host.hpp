@@ -30,10 +30,11 @@ inline int ilog2(int64_t v) {
   return r;
 }
 
-// Stage twiddle table of the line plan of L: for each stage st >= 1 the
-// block [s][k] = W_{NS RAD}^{k s} (s < RAD, k < NS).  Allocates *out.
-inline dd_status make_stage_table(void** out, int L, bool dbl, bool fp32, hipStream_t s) {
-  const LinePlan lp = make_line_plan(L);
+// Stage twiddle table of the line plan of L (narrow: the one-pass kernels'
+// plan, single_narrow): for each stage st >= 1 the block
+// [s][k] = W_{NS RAD}^{k s} (s < RAD, k < NS).  Allocates *out.
+inline dd_status make_stage_table(void** out, int L, bool dbl, bool fp32, hipStream_t s, bool narrow = false) {
+  const LinePlan lp = make_line_plan(L, narrow);
   const int n = line_tw_size(lp);
   const size_t cxb = dbl ? 16 : 8;
   hipError_t e = hipMalloc(out, (size_t)(n > 0 ? n : 1) * cxb);

@@ -32,7 +32,7 @@ template <typename R, int L>
 __device__ __forceinline__ void body_single_inv(const cx<R>* __restrict__ X, cx<R>* __restrict__ x,
                                                 const DenseArgs<R>& a, int64_t bid, int nt, unsigned char* smem,
                                                 int tid) {
-  constexpr LinePlan P = make_line_plan(L);
+  constexpr LinePlan P = make_line_plan(L, single_narrow(L));
   constexpr int EPT = P.EPT;
   constexpr int TL = L / EPT;
   cx<R>* ex = reinterpret_cast<cx<R>*>(smem);
@@ -56,7 +56,7 @@ __device__ __forceinline__ void body_single_inv(const cx<R>* __restrict__ X, cx<
     cx<R> v[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) v[e] = active ? cconj(im[a.alpha * (t + TL * e) + j]) : cx<R>{(R)0, (R)0};
-    line_fft<R, L, (TL <= 64)>(v, t, ex, lay, a.twL, act);
+    line_fft<R, L, (TL <= 64), single_narrow(L)>(v, t, ex, lay, a.twL, act);
     if (j == 0) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) acc[e] = cadd(acc[e], v[e]);

@@ -124,6 +124,8 @@ __host__ __device__ constexpr int pass2_lds_elems(int L, int RB, int rows = 0) {
 constexpr int LDS_PASS_MAX = 160 * 1024;
 
 constexpr int line_threads(int L) { return L / make_line_plan(L).EPT; }
+// Threads per line of the one-pass kernels (their plan: single_narrow).
+constexpr int single_line_threads(int L) { return L / make_line_plan(L, single_narrow(L)).EPT; }
 
 // Launch geometry shared by host and device.
 template <int L, int RBYTES>
@@ -145,8 +147,9 @@ struct Geom {
   }
   static constexpr int BLOCK_PASS = TL * lines_pass();
   // single pass: up to 256 threads (one line if TL >= 256)
-  static constexpr int lines_single() { return TL >= 256 ? 1 : 256 / TL; }
-  static constexpr int BLOCK_SINGLE = TL * lines_single();
+  static constexpr int TLS = single_line_threads(L);
+  static constexpr int lines_single() { return TLS >= 256 ? 1 : 256 / TLS; }
+  static constexpr int BLOCK_SINGLE = TLS * lines_single();
 };
 
 // ---------------------------------------------------------------------------
@@ -161,7 +164,7 @@ struct Geom {
 template <typename R, class InAcc, int L>
 __device__ __forceinline__ void body_single(const InAcc& x, cx<R>* __restrict__ X, const DenseArgs<R>& a,
                                             int64_t bid, int nt, unsigned char* smem, int tid) {
-  constexpr LinePlan P = make_line_plan(L);
+  constexpr LinePlan P = make_line_plan(L, single_narrow(L));
   constexpr int EPT = P.EPT;
   constexpr int TL = L / EPT;
   cx<R>* ex = reinterpret_cast<cx<R>*>(smem);
@@ -194,7 +197,7 @@ __device__ __forceinline__ void body_single(const InAcc& x, cx<R>* __restrict__ 
 #pragma unroll
       for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pre[TL * e]);
     }
-    line_fft<R, L, (TL <= 64)>(v, t, ex, lay, a.twL, act);
+    line_fft<R, L, (TL <= 64), single_narrow(L)>(v, t, ex, lay, a.twL, act);
     if (act) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) im[a.alpha * (t + TL * e) + j] = v[e];
@@ -226,7 +229,7 @@ __host__ __device__ constexpr int single_groups_lds_elems(int groups, int alpha)
 template <typename R, class InAcc, int L>
 __device__ __forceinline__ void body_single_groups(const InAcc& x, cx<R>* __restrict__ X, const DenseArgs<R>& a,
                                                    int64_t sig, int groups, int nt, unsigned char* smem, int tid) {
-  constexpr LinePlan P = make_line_plan(L);
+  constexpr LinePlan P = make_line_plan(L, single_narrow(L));
   constexpr int EPT = P.EPT;
   constexpr int TL = L / EPT;
   cx<R>* ex = reinterpret_cast<cx<R>*>(smem);
@@ -254,7 +257,7 @@ __device__ __forceinline__ void body_single_groups(const InAcc& x, cx<R>* __rest
 #pragma unroll
       for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pre[TL * e]);
     }
-    line_fft<R, L, (TL <= 64)>(v, t, ex, lay, a.twL, act);
+    line_fft<R, L, (TL <= 64), single_narrow(L)>(v, t, ex, lay, a.twL, act);
     if (act) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) img[a.alpha * (t + TL * e) + j] = v[e];

@@ -50,8 +50,8 @@ KGeom geom_single(int L, int rbytes) {
 #define DD_CASE(LL)                                                                                   \
   case LL:                                                                                            \
     if (rbytes == 4)                                                                                  \
-      return {Geom<LL, 4>::TL, Geom<LL, 4>::lines_single(), Geom<LL, 4>::BLOCK_SINGLE};               \
-    return {Geom<LL, 8>::TL, Geom<LL, 8>::lines_single(), Geom<LL, 8>::BLOCK_SINGLE};
+      return {Geom<LL, 4>::TLS, Geom<LL, 4>::lines_single(), Geom<LL, 4>::BLOCK_SINGLE};              \
+    return {Geom<LL, 8>::TLS, Geom<LL, 8>::lines_single(), Geom<LL, 8>::BLOCK_SINGLE};
     DD_ALL_LENGTHS(DD_CASE)
 #undef DD_CASE
     default:
@@ -73,7 +73,7 @@ KGeom geom_pass(int L, int rbytes) {
 }
 
 // Every instantiated length has a consistent radix plan.
-#define DD_CASE(LL) static_assert(line_plan_ok(LL), "bad line plan");
+#define DD_CASE(LL) static_assert(line_plan_ok(LL) && line_plan_ok(LL, single_narrow(LL)), "bad line plan");
 DD_ALL_LENGTHS(DD_CASE)
 #undef DD_CASE
 
