@@ -31,6 +31,7 @@
 #include "../../include/dense_dft.h"
 #include "dd_batch_host.hpp"
 #include "dd_launch.hpp"
+#include "dd_admit.hpp"
 #include "dd_pool.hpp"
 
 using namespace dd;
@@ -147,33 +148,17 @@ void finish(dd_server* s, Req* r, dd_status st, uint64_t t) {
 bool launch_slot(dd_server* s, Slot& slot, std::unique_lock<std::mutex>& lk) {
   const int cap = plain_mode(s) ? 1 : s->cfg.max_batch;
   std::vector<Req*> take;
-  auto admit = [&](Req* r) {
+  // claims a request's share of the budget and its scratch from the pool
+  auto reserve = [&](Req* r) {
     if (s->used + r->footprint > s->cfg.hbm_budget_bytes) return false;
     size_t off = 0;
     if (r->scratch && !s->ranges.alloc(r->scratch, &off)) return false;
     r->scratch_off = off;
     s->used += r->footprint;
     s->stats.peak_footprint = std::max(s->stats.peak_footprint, s->used);
-    take.push_back(r);
     return true;
   };
-  if (!s->pending.empty() && (plain_mode(s) || !s->pending.front()->kernel)) {
-    // a request outside the batch kernel (large, FP64, or a length the
-    // kernel is not built for) takes a slot of its own, so that its plain
-    // execution overlaps the batches on the other slots' streams
-    if (admit(s->pending.front())) s->pending.pop_front();
-  } else {
-    // a batch gathers the kernel requests in arrival order and steps over
-    // the others, which the next free slot takes; it stops at the first
-    // kernel request that does not fit, so those keep their order
-    int scanned = 0;
-    for (auto it = s->pending.begin(); it != s->pending.end() && (int)take.size() < cap && scanned < 4 * cap;
-         ++scanned) {
-      if (!(*it)->kernel) { ++it; continue; }
-      if (!admit(*it)) break;
-      it = s->pending.erase(it);
-    }
-  }
+  admit_requests(s->pending, cap, plain_mode(s), [](const Req* r) { return r->kernel; }, reserve, take);
   if (take.empty()) return false;
   slot.busy = true;
   lk.unlock();

@@ -1,6 +1,6 @@
-"""Serving-path checks that need no GPU: the pool bookkeeping (built with g++
-from its plain C++ header and run), and the server API's argument checks,
-which return before any device call."""
+"""Serving-path checks that need no GPU: the pool bookkeeping and the
+admission policy (each built with g++ from its plain C++ header and run),
+and the server API's argument checks, which return before any device call."""
 import ctypes
 import os
 import subprocess
@@ -17,6 +17,15 @@ def test_pool_bookkeeping(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.strip().endswith("OK")
+
+
+def test_admission_policy(tmp_path):
+    exe = tmp_path / "admit_check"
+    subprocess.run(["g++", "-std=c++17", "-O2", "-Wall", "-Werror",
+                    os.path.join(ROOT, "tests", "host", "admit_check.cpp"), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.strip().endswith("admission checks passed")
 
 
 @pytest.mark.parametrize("field,value", [
