@@ -221,7 +221,7 @@ typedef struct dd_tune_info {
  * problem class with (one pass at each block width; each two-pass split
  * N1*N2 with each j-group), on temporary buffers of the problem's size, and
  * record the fastest in the process's tuning table under (N, alpha,
- * precision of dtype, batch size class floor(log2(batch))).  Later
+ * dtype, batch size class floor(log2(batch))).  Later
  * dense_dft_plan calls of that class use it.  Synchronous.
  * Errors: as dense_dft_plan, DD_ERR_NOMEM, DD_ERR_DEVICE. */
 dd_status dense_dft_tune(int64_t N, int32_t alpha, int64_t batch, dd_dtype dtype,
@@ -236,7 +236,9 @@ dd_status dense_dft_tune(int64_t N, int32_t alpha, int64_t batch, dd_dtype dtype
 dd_status dense_dft_tune_batch(int64_t N, int32_t alpha, dd_tune_info *info);
 
 /* Write the tuning table to a text file / merge one into it (entries of the
- * file replace those of the same class).  A file named by the environment
+ * file replace those of the same class; lines of the earlier format, keyed
+ * by precision, serve both input dtypes of that precision).  A file named by
+ * the environment
  * variable DD_TUNE_DB is merged at the first use of the table.  Entries are
  * re-validated when used: one the kernels cannot run falls back to the
  * planner's rule.  Errors: DD_ERR_INVALID (null path, file not writable /

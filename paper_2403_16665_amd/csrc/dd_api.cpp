@@ -261,7 +261,7 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
 // kernels can run, else the built-in rules.
 dd_status configure_auto(dd_plan* p) {
   dd_sched sc;
-  if (tune_lookup_plan(p->N, p->alpha, p->dbl, p->batch, &sc) && configure(p, sc) == DD_OK) return DD_OK;
+  if (tune_lookup_plan(p->N, p->alpha, (int)p->dtype, p->batch, &sc) && configure(p, sc) == DD_OK) return DD_OK;
   return default_sched(p->N, p->alpha, p->rbytes, &sc) ? configure(p, sc) : DD_ERR_UNSUPPORTED;
 }
 

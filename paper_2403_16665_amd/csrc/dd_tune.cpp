@@ -31,7 +31,7 @@ struct Entry {
 };
 
 std::mutex g_mu;
-std::map<std::tuple<int64_t, int, int, int>, Entry> g_plan;  // N, alpha, double precision, batch class
+std::map<std::tuple<int64_t, int, int, int>, Entry> g_plan;  // N, alpha, input dtype, batch class
 std::map<std::pair<int64_t, int>, Entry> g_batch;            // N, alpha
 bool g_env_checked = false;
 
@@ -50,16 +50,26 @@ bool load_locked(const char* path) {
     int alpha, dbl, bclass, passes, lines, jgroup;
     float ms;
     dd_sched s{};
-    if (std::sscanf(line, "plan %lld %d %d %d %d %d %lld %lld %d %lld %f", &N, &alpha, &dbl, &bclass, &passes, &lines,
-                    &N1, &N2, &jgroup, &chunk, &ms) == 11) {
+    int dtype = -1;
+    // plan2 (keyed by input dtype); plan (earlier files, keyed by precision:
+    // the entry serves both input dtypes of that precision)
+    const bool v2 = std::sscanf(line, "plan2 %lld %d %d %d %d %d %lld %lld %d %lld %f", &N, &alpha, &dtype, &bclass,
+                                &passes, &lines, &N1, &N2, &jgroup, &chunk, &ms) == 11;
+    const bool v1 = !v2 && std::sscanf(line, "plan %lld %d %d %d %d %d %lld %lld %d %lld %f", &N, &alpha, &dbl,
+                                       &bclass, &passes, &lines, &N1, &N2, &jgroup, &chunk, &ms) == 11;
+    if (v1 || v2) {
       s.passes = passes;
       s.lines = lines;
       s.N1 = N1;
       s.N2 = N2;
       s.jgroup = jgroup;
       s.chunk = chunk;
-      if (N >= 1 && alpha >= 1 && (dbl == 0 || dbl == 1) && bclass >= 0 && bclass <= 12 && sched_sane(s))
-        g_plan[std::make_tuple((int64_t)N, alpha, dbl, bclass)] = Entry{s, ms};
+      const bool ok = N >= 1 && alpha >= 1 && bclass >= 0 && bclass <= 12 && sched_sane(s);
+      if (ok && v2 && dtype >= DD_F32 && dtype <= DD_C128)
+        g_plan[std::make_tuple((int64_t)N, alpha, dtype, bclass)] = Entry{s, ms};
+      if (ok && v1 && (dbl == 0 || dbl == 1))
+        for (int d : {dbl ? (int)DD_F64 : (int)DD_F32, dbl ? (int)DD_C128 : (int)DD_C64})
+          g_plan[std::make_tuple((int64_t)N, alpha, d, bclass)] = Entry{s, ms};
     } else if (std::sscanf(line, "batch %lld %d %d %lld %lld %f", &N, &alpha, &passes, &N1, &N2, &ms) == 6) {
       s.passes = passes;
       s.N1 = N1;
@@ -116,19 +126,19 @@ int tune_batch_class(int64_t batch) {
   return b;
 }
 
-bool tune_lookup_plan(int64_t N, int alpha, bool dbl, int64_t batch, dd_sched* out) {
+bool tune_lookup_plan(int64_t N, int alpha, int dtype, int64_t batch, dd_sched* out) {
   std::lock_guard<std::mutex> g(g_mu);
   env_once_locked();
-  auto it = g_plan.find(std::make_tuple(N, alpha, dbl ? 1 : 0, tune_batch_class(batch)));
+  auto it = g_plan.find(std::make_tuple(N, alpha, dtype, tune_batch_class(batch)));
   if (it == g_plan.end()) return false;
   *out = it->second.s;
   return true;
 }
 
-void tune_store_plan(int64_t N, int alpha, bool dbl, int64_t batch, const dd_sched& s, float ms) {
+void tune_store_plan(int64_t N, int alpha, int dtype, int64_t batch, const dd_sched& s, float ms) {
   std::lock_guard<std::mutex> g(g_mu);
   env_once_locked();
-  g_plan[std::make_tuple(N, alpha, dbl ? 1 : 0, tune_batch_class(batch))] = Entry{s, ms};
+  g_plan[std::make_tuple(N, alpha, dtype, tune_batch_class(batch))] = Entry{s, ms};
 }
 
 bool tune_lookup_batch(int64_t N, int alpha, dd_sched* out) {
@@ -217,7 +227,7 @@ dd_status dense_dft_tune(int64_t N, int32_t alpha, int64_t batch, dd_dtype dtype
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (st != DD_OK) return st;
-  tune_store_plan(N, alpha, dbl, batch, best_s, best);
+  tune_store_plan(N, alpha, (int)dtype, batch, best_s, best);
   info->best = best_s;
   info->ms_best = best;
   info->ms_default = t_def;
@@ -289,11 +299,11 @@ dd_status dense_dft_tune_save(const char* path) {
   env_once_locked();
   FILE* f = std::fopen(path, "w");
   if (!f) return DD_ERR_INVALID;
-  std::fprintf(f, "# dense_dft tuning table v1\n");
-  std::fprintf(f, "# plan N alpha double batch_class passes lines N1 N2 jgroup chunk ms\n");
+  std::fprintf(f, "# dense_dft tuning table v2\n");
+  std::fprintf(f, "# plan2 N alpha input_dtype batch_class passes lines N1 N2 jgroup chunk ms\n");
   for (const auto& kv : g_plan) {
     const dd_sched& s = kv.second.s;
-    std::fprintf(f, "plan %lld %d %d %d %d %d %lld %lld %d %lld %.6g\n", (long long)std::get<0>(kv.first),
+    std::fprintf(f, "plan2 %lld %d %d %d %d %d %lld %lld %d %lld %.6g\n", (long long)std::get<0>(kv.first),
                  std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), s.passes, s.lines,
                  (long long)s.N1, (long long)s.N2, s.jgroup, (long long)s.chunk, kv.second.ms);
   }

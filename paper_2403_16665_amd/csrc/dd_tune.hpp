@@ -1,5 +1,5 @@
 // dd_tune.hpp -- the process-wide tuning table: schedules measured by the
-// tuner (dd_tune.cpp) for plain plans, keyed by (N, alpha, precision,
+// tuner (dd_tune.cpp) for plain plans, keyed by (N, alpha, input dtype,
 // batch size class), and for the batch kernel, keyed by (N, alpha).
 #pragma once
 
@@ -14,8 +14,8 @@ struct Sched;
 // Batch size class of a plain plan: floor(log2(batch)), at most 12.
 int tune_batch_class(int64_t batch);
 
-bool tune_lookup_plan(int64_t N, int alpha, bool dbl, int64_t batch, dd_sched* out);
-void tune_store_plan(int64_t N, int alpha, bool dbl, int64_t batch, const dd_sched& s, float ms);
+bool tune_lookup_plan(int64_t N, int alpha, int dtype, int64_t batch, dd_sched* out);
+void tune_store_plan(int64_t N, int alpha, int dtype, int64_t batch, const dd_sched& s, float ms);
 bool tune_lookup_batch(int64_t N, int alpha, dd_sched* out);
 void tune_store_batch(int64_t N, int alpha, const dd_sched& s, float ms);
 

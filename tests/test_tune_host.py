@@ -73,7 +73,8 @@ def test_table_load_save_clear_and_planner_use(dd, tmp_path):
     src = tmp_path / "in.txt"
     src.write_text(TABLE)
     dd.dense_dft_tune_load(str(src))
-    assert dd.dense_dft_tune_entries() == (2, 2)
+    # each "plan" line (keyed by precision) serves both input dtypes of it
+    assert dd.dense_dft_tune_entries() == (4, 2)
     # the planner's choice (first candidate) is now the table's schedule
     first = dd.dense_dft_sched_candidates(1024, 16, 1, dd.DD_C64)[0]
     assert (first.passes, first.N1, first.N2, first.jgroup) == (2, 32, 32, 4)
@@ -84,11 +85,11 @@ def test_table_load_save_clear_and_planner_use(dd, tmp_path):
     out = tmp_path / "out.txt"
     dd.dense_dft_tune_save(str(out))
     lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
-    assert len(lines) == 4
+    assert len(lines) == 6 and sum(l.startswith("plan2 ") for l in lines) == 4
     dd.dense_dft_tune_clear()
     assert dd.dense_dft_tune_entries() == (0, 0)
     dd.dense_dft_tune_load(str(out))
-    assert dd.dense_dft_tune_entries() == (2, 2)
+    assert dd.dense_dft_tune_entries() == (4, 2)
     with pytest.raises(dd.DenseDFTError):
         dd.dense_dft_tune_load(str(tmp_path / "missing.txt"))
 
@@ -103,7 +104,20 @@ def test_table_from_environment(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, env=env,
                          timeout=120)
     assert out.returncode == 0, out.stderr
-    assert out.stdout.split("\n")[:2] == ["(2, 2)", "32 32 4"]
+    assert out.stdout.split("\n")[:2] == ["(4, 2)", "32 32 4"]
+
+
+def test_table_entries_per_input_dtype(dd, tmp_path):
+    """A plan2 entry is keyed by input dtype: it serves real float32 plans of
+    its class and leaves complex64 plans of the same class to the rule."""
+    src = tmp_path / "v2.txt"
+    src.write_text("plan2 65536 8 0 8 2 0 512 128 8 32 0.6\n")
+    dd.dense_dft_tune_load(str(src))
+    assert dd.dense_dft_tune_entries() == (1, 0)
+    real = dd.dense_dft_sched_candidates(65536, 8, 256, dd.DD_F32)[0]
+    cplx = dd.dense_dft_sched_candidates(65536, 8, 256, dd.DD_C64)[0]
+    assert (real.N1, real.N2) == (512, 128)
+    assert (cplx.N1, cplx.N2) == (256, 256)
 
 
 def test_tune_null_arguments(dd):
