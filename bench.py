@@ -91,10 +91,11 @@ def make_inputs(name, w):
     raise ValueError(name)
 
 
-def tune_classes(dd, classes, batch_kernel=True, plain_batch=1):
+def tune_classes(dd, classes, batch_kernel=True, plain_batch=1, dtypes=None):
     """Run the schedule tuner over (N, alpha) classes before timing: the batch
     kernel's schedule per class and, if plain_batch, the plain plan's (for a
-    batch of plain_batch complex64 signals).  Returns a summary."""
+    batch of plain_batch signals of each input dtype in `dtypes`, complex64
+    by default).  Returns a summary."""
     t0 = time.perf_counter()
     gain_b, gain_p = [], []
     for N, a in sorted(set(classes)):
@@ -105,8 +106,9 @@ def tune_classes(dd, classes, batch_kernel=True, plain_batch=1):
             except dd.DenseDFTError:
                 pass   # no batch-kernel schedule: plain fallback
         if plain_batch:
-            r = dd.dense_dft_tune(N, a, plain_batch, dd.DD_C64)
-            gain_p.append(r["ms_default"] / r["ms_best"])
+            for code in (dtypes or (dd.DD_C64,)):
+                r = dd.dense_dft_tune(N, a, plain_batch, code)
+                gain_p.append(r["ms_default"] / r["ms_best"])
     out = {"classes": len(set(classes)), "seconds": time.perf_counter() - t0}
     if gain_b:
         out["batch_kernel_speedup_over_rule"] = {"mean": float(np.mean(gain_b)), "max": float(np.max(gain_b))}
@@ -302,7 +304,7 @@ def run_serving(args):
                 "hbm_GBps": float(balg.sum() / span / 1e9), "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "mean_batch": float(np.mean([r["batch_requests"] for r in res]))}
 
-    tuning = tune_classes(dd, mix) if args.tune else None
+    tuning = tune_classes(dd, mix, dtypes=(dd.DD_C64, dd.DD_F32)) if args.tune else None
     out = {}
     for mode, name in ((dd.DD_SERVE_PLAIN, "plain"), (dd.DD_SERVE_BATCHED, "batched")):
         srv = dd.dense_dft_server_create(mode=mode, hbm_budget_bytes=budget)
