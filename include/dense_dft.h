@@ -33,7 +33,9 @@
  *     conj(X_m), which then hold exactly.
  *   - Execution calls only enqueue work on the given HIP stream (NULL = the
  *     default stream) and return at once; device faults surface at the
- *     caller's synchronisation or as DD_ERR_DEVICE from a later call.
+ *     caller's synchronisation or as DD_ERR_DEVICE from a later call.  With
+ *     DD_DEBUG set in the environment, a kernel launch that HIP refuses is
+ *     reported on stderr with its grid, block and LDS size.
  *   - Thread safety: a plan is immutable after creation; concurrent
  *     executions of one plan must use distinct workspaces.
  */
