@@ -57,3 +57,59 @@ def test_random_configuration(oracle_mod, seed):
         full = None if len(bins) == M else spectrum_rms(x[b], T)
         assert_close(X[b][bins], oracle_mod.alpha_dft_bins(x[b], alpha, T, bins), kind, f"{what} signal {b}",
                      full_rms=full)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_random_batch_mix(oracle_mod, seed):
+    """One persistent batch of 12 random items (lengths the batch kernel is
+    built for and others, real float32 and complex64, alpha up to 17):
+    sampled bins of every item against the oracle."""
+    import torch
+    import paper_2403_16665_amd as dd
+    rng = np.random.default_rng(1000 + seed)
+    small = [n for n in LENGTHS if 16 <= n <= (1 << 16)]
+    items, xs, Xs = [], [], []
+    for _ in range(12):
+        N = int(rng.choice(small))
+        alpha = int(rng.integers(1, 18))
+        real = bool(rng.integers(0, 2))
+        x = rng.standard_normal(N).astype(np.float32) if real else \
+            (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64)
+        xs.append(torch.from_numpy(x).cuda())
+        Xs.append(torch.zeros(alpha * N, dtype=torch.complex64, device="cuda"))
+        items.append((N, alpha, N * 1e-3, dd.DD_F32 if real else dd.DD_C64, x))
+    torch.cuda.synchronize()
+    dd.dense_dft_exec_many([(N, a, T, c, xs[i], Xs[i]) for i, (N, a, T, c, _) in enumerate(items)])
+    for i, (N, a, T, c, x) in enumerate(items):
+        bins = siggen.bin_subset(rng, a * N, 96)
+        full = None if len(bins) == a * N else spectrum_rms(x, T)
+        assert_close(Xs[i].cpu().numpy()[bins], oracle_mod.alpha_dft_bins(x, a, T, bins), "f32",
+                     f"seed {seed} item {i}: N={N} alpha={a} dtype={c}", full_rms=full)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_random_inverse(oracle_mod, seed):
+    """Inverse transforms of random spectra in both precisions, with the
+    planner's schedule or a random candidate: sampled outputs against the
+    oracle's inverse."""
+    import torch
+    import paper_2403_16665_amd as dd
+    rng, N, alpha, batch, code, random_sched = draw(2000 + seed)
+    cplx = np.complex128 if code in (dd.DD_F64, dd.DD_C128) else np.complex64
+    code = dd.DD_C128 if cplx == np.complex128 else dd.DD_C64
+    M = alpha * N
+    X = (rng.standard_normal((batch, M)) + 1j * rng.standard_normal((batch, M))).astype(cplx)
+    T = float(rng.uniform(0.1, 10.0))
+    if random_sched:
+        cands = dd.dense_dft_sched_candidates(N, alpha, batch, code)
+        plan = dd.dense_dft_plan_sched(N, alpha, T, batch, code, cands[int(rng.integers(0, len(cands)))])
+    else:
+        plan = dd.dense_dft_plan(N, alpha, T, batch, code)
+    x = plan.exec_inverse(torch.from_numpy(X).cuda()).cpu().numpy()
+    kind = "f64" if code == dd.DD_C128 else "f32"
+    for b in range(batch):
+        samples = siggen.bin_subset(rng, N, 96)
+        ref = oracle_mod.inverse_alpha_dft_samples(X[b], alpha, T, samples)
+        full = None if len(samples) == N else np.sqrt(np.mean(np.abs(ref) ** 2))
+        assert_close(x[b][samples], ref, kind, f"seed {seed}: inverse N={N} alpha={alpha} batch={batch}",
+                     full_rms=full)
