@@ -245,6 +245,16 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
                   cu / with_q == cu / p->p1_lds ? 1 : 0;
     if (p->p1_q_lds) p->p1_lds = with_q;
   }
+  // a chunk's launches must stay within one dispatch's grid: the default
+  // chunk shrinks to fit, a requested one that does not fit is refused
+  {
+    const int64_t b1 = max_launch_blocks(p->p1_lines * p->p1_TL) / ((int64_t)p->p1_ntile * p->p1_njg);
+    const int64_t b2 = max_launch_blocks((p->p2_lines + 1) * p->p2_TL) / p->p2_ntile;
+    const int64_t cap = b1 < b2 ? b1 : b2;
+    if (cap < 1 || (sc.chunk > 0 && chunk > cap)) return DD_ERR_UNSUPPORTED;
+    if (chunk > cap) chunk = cap;
+    p->chunk = chunk;
+  }
   const size_t inv_pre = (size_t)alpha * N1 * cx_bytes(p);
   p->inv_pre_lds =
       inv_pre <= 16 * 1024 && lds_pass1((int)N1, g1.lines, p->rbytes, alpha * (int)N1) <= (size_t)LDS_PASS_MAX ? 1 : 0;
@@ -523,8 +533,16 @@ dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s
     a.scale = scale;
     a.twL = static_cast<const cx<R>*>(p->twL1);
     a.twPre = static_cast<const cx<R>*>(p->twPre);
-    LaunchCfg c{(p->batch + p->s_lines - 1) / p->s_lines, p->s_lines * p->s_TL, p->s_lds, s};
-    return hip_status(timed_launch(p, 1, s, [&] { return launch_single((int)p->N, c, x, X, a); }));
+    const int block = p->s_lines * p->s_TL;
+    const int64_t per = max_launch_blocks(block) * p->s_lines;  // signals per launch
+    for (int64_t b0 = 0; b0 < p->batch; b0 += per) {
+      a.batch = p->batch - b0 < per ? p->batch - b0 : per;
+      LaunchCfg c{(a.batch + p->s_lines - 1) / p->s_lines, block, p->s_lds, s};
+      const hipError_t e =
+          timed_launch(p, 1, s, [&] { return launch_single((int)p->N, c, x + b0 * p->N, X + b0 * M, a); });
+      if (e != hipSuccess) return hip_status(e);
+    }
+    return DD_OK;
   }
   for (int64_t c0 = 0; c0 < p->batch; c0 += p->chunk) {
     const int64_t nb = p->batch - c0 < p->chunk ? p->batch - c0 : p->chunk;
@@ -586,8 +604,16 @@ dd_status exec_inverse_typed(dd_plan* p, const cx<R>* X, cx<R>* x, cx<R>* ws, hi
     a.scale = scale;
     a.twL = static_cast<const cx<R>*>(p->twL1);
     a.twPre = static_cast<const cx<R>*>(p->twPre);
-    LaunchCfg c{(p->batch + p->s_lines - 1) / p->s_lines, p->s_lines * p->s_TL, p->s_lds, s};
-    return hip_status(timed_launch(p, 4, s, [&] { return launch_single_inv((int)p->N, c, X, x, a); }));
+    const int block = p->s_lines * p->s_TL;
+    const int64_t per = max_launch_blocks(block) * p->s_lines;  // signals per launch
+    for (int64_t b0 = 0; b0 < p->batch; b0 += per) {
+      a.batch = p->batch - b0 < per ? p->batch - b0 : per;
+      LaunchCfg c{(a.batch + p->s_lines - 1) / p->s_lines, block, p->s_lds, s};
+      const hipError_t e =
+          timed_launch(p, 4, s, [&] { return launch_single_inv((int)p->N, c, X + b0 * M, x + b0 * p->N, a); });
+      if (e != hipSuccess) return hip_status(e);
+    }
+    return DD_OK;
   }
   for (int64_t c0 = 0; c0 < p->batch; c0 += p->chunk) {
     const int64_t nb = p->batch - c0 < p->chunk ? p->batch - c0 : p->chunk;

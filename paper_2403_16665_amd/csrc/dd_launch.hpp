@@ -84,6 +84,11 @@ inline size_t lds_pass2(int L, int lines, int rbytes, int rows = 0) {
   return (size_t)pass2_lds_elems(L, lines, rows) * 2 * rbytes;
 }
 
+// A dispatch's grid size is a 32-bit count of work-items; launches are kept
+// below 2^31 of them, and larger batches are split over several launches.
+constexpr int64_t MAX_LAUNCH_ITEMS = 0x7fffffff;
+inline int64_t max_launch_blocks(int block) { return block > 0 ? MAX_LAUNCH_ITEMS / block : 0; }
+
 // With DD_DEBUG set in the environment, a failed launch is reported on
 // stderr with its geometry.
 inline hipError_t report_launch(hipError_t e, const char* what, const LaunchCfg& c) {
@@ -105,6 +110,7 @@ inline hipError_t launch_kernel(K kern, const LaunchCfg& c, Args... args) {
     }
   }
   if (c.grid <= 0) return hipSuccess;
+  if (c.grid > max_launch_blocks(c.block)) return report_launch(hipErrorInvalidConfiguration, "grid size", c);
   hipLaunchKernelGGL(kern, dim3((unsigned)c.grid), dim3(c.block), c.lds, c.stream, args...);
   return report_launch(hipGetLastError(), "kernel launch", c);
 }

@@ -92,6 +92,25 @@ def test_chunk_candidates():
     assert chunks == {32}
 
 
+def test_schedules_fit_one_dispatch():
+    """A launch's grid is a 32-bit count of work-items, so a schedule whose
+    pass-1 grid would exceed 2^31 of them is neither offered nor accepted:
+    at N = 4, alpha = 2^28 one j per block would take 2^28 blocks per
+    signal, and a requested chunk of 2^31 signals of N = 8 as many blocks."""
+    import ctypes
+    import paper_2403_16665_amd as dd
+    two = [sc for sc in dd.dense_dft_sched_candidates(4, 1 << 28, 1, 1) if sc.passes == 2]
+    # blocks of at least one wave: 2^28 / jgroup blocks of 64 work-items fit only for jgroup >= 8
+    assert two and all(sc.jgroup >= 8 for sc in two), sorted({sc.jgroup for sc in two})
+    assert any(sc.jgroup == 1 for sc in dd.dense_dft_sched_candidates(4, 1 << 12, 1, 1) if sc.passes == 2)
+    for dtype in (0, 1, 2, 3):
+        h = ctypes.c_void_p(12345)
+        sc = dd.make_sched(2, N1=2, N2=4, chunk=1 << 31)
+        rc = dd._lib.dense_dft_plan_sched(ctypes.byref(h), 8, 1, 1.0, 1 << 31, dtype, dd.DD_TWIDDLE_FP64,
+                                          ctypes.byref(sc))
+        assert rc == 2 and not h.value
+
+
 def test_null_handles_rejected():
     import ctypes
     import paper_2403_16665_amd as dd
