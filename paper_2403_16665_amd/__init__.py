@@ -223,6 +223,39 @@ def _ptr(t):
     return None if t is None else _vp(t.data_ptr())
 
 
+def in_dtype(code: int):
+    """torch dtype of a DD_* input code."""
+    import torch
+    return {DD_F32: torch.float32, DD_C64: torch.complex64, DD_F64: torch.float64,
+            DD_C128: torch.complex128}[code]
+
+
+def _check_buf(t, what: str, dtype, numel: int) -> None:
+    """The C ABI sees only an address, so a tensor the kernels will read or
+    write is checked here: on the device, of the plan's dtype, contiguous,
+    and holding at least the ``numel`` elements the launch touches.  Raises
+    DenseDFTError with DD_ERR_INVALID, as the library does for bad arguments."""
+    if not getattr(t, "is_cuda", False):
+        where = f" on {t.device}" if hasattr(t, "device") else ""
+        raise DenseDFTError(1, f"{what}: expected a device (cuda) tensor, got {type(t).__name__}{where}")
+    if t.dtype != dtype:
+        raise DenseDFTError(1, f"{what}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise DenseDFTError(1, f"{what}: the tensor must be contiguous")
+    if t.numel() < numel:
+        raise DenseDFTError(1, f"{what}: {t.numel()} elements, the transform needs {numel}")
+
+
+def _check_workspace(plan, workspace) -> None:
+    if workspace is None:
+        return
+    if not getattr(workspace, "is_cuda", False) or not workspace.is_contiguous():
+        raise DenseDFTError(1, "workspace: expected a contiguous device (cuda) tensor")
+    have, need = workspace.numel() * workspace.element_size(), dense_dft_workspace_size(plan)
+    if have < need:
+        raise DenseDFTError(1, f"workspace: {have} bytes, the plan needs {need}")
+
+
 def dense_dft_exec(plan: Plan, x, X, workspace=None, stream=None) -> None:
     """Enqueue the plan on ``stream`` (default: torch's current stream).
 
@@ -230,6 +263,9 @@ def dense_dft_exec(plan: Plan, x, X, workspace=None, stream=None) -> None:
     [batch, alpha*N]; workspace: optional device tensor of at least
     dense_dft_workspace_size(plan) bytes.
     """
+    _check_buf(x, "x", in_dtype(plan.dtype), plan.batch * plan.N)
+    _check_buf(X, "X", out_dtype(plan.dtype), plan.batch * plan.M)
+    _check_workspace(plan, workspace)
     if stream is None:
         import torch
         stream = torch.cuda.current_stream(x.device).cuda_stream
@@ -358,9 +394,7 @@ def _desc_array(descs):
         if isinstance(d, dd_desc):
             arr[i] = d
         else:
-            N, alpha, T, dtype, x, X = d
-            arr[i] = dd_desc(int(N), int(alpha), float(T), int(dtype),
-                             None if x is None else x.data_ptr(), None if X is None else X.data_ptr())
+            arr[i] = _one_desc(d, f"descriptor {i}")
     return arr, len(items)
 
 
@@ -498,11 +532,20 @@ def dense_dft_server_warm(server: Server, N: int, alpha: int, T: float, dtype: i
            "dense_dft_server_warm")
 
 
-def _one_desc(d) -> dd_desc:
+def _one_desc(d, what: str = "request") -> dd_desc:
+    """dd_desc from (N, alpha, T, dtype, x_tensor, X_tensor); the tensors are
+    checked against N, alpha and dtype (None passes as NULL, which the library
+    refuses).  A dd_desc passes through unchecked."""
     if isinstance(d, dd_desc):
         return d
     N, alpha, T, dtype, x, X = d
-    return dd_desc(int(N), int(alpha), float(T), int(dtype), x.data_ptr(), X.data_ptr())
+    if dtype in (DD_F32, DD_C64, DD_F64, DD_C128) and int(N) > 0 and int(alpha) > 0:
+        if x is not None:
+            _check_buf(x, f"{what}: x", in_dtype(dtype), int(N))
+        if X is not None:
+            _check_buf(X, f"{what}: X", out_dtype(dtype), int(alpha) * int(N))
+    return dd_desc(int(N), int(alpha), float(T), int(dtype), None if x is None else x.data_ptr(),
+                   None if X is None else X.data_ptr())
 
 
 def dense_dft_submit(server: Server, desc, t_arrival_ns: int | None = None) -> int:
@@ -618,9 +661,13 @@ def decimated_dft(x, p: int, T: float, flags: int = DD_TWIDDLE_FP64, plan: Plan 
 
 def dense_dft_exec_inverse(plan: Plan, X, x, workspace=None, stream=None) -> None:
     """Inverse transform of device spectra X ([batch][alpha*N]) into x ([batch][N] complex)."""
+    if not getattr(plan, "p", 0):  # (alpha = 1/p plans are refused by the library: one-way)
+        _check_buf(X, "X", out_dtype(plan.dtype), plan.batch * plan.alpha * plan.N)
+        _check_buf(x, "x", out_dtype(plan.dtype), plan.batch * plan.N)
+        _check_workspace(plan, workspace)
     if stream is None:
         import torch
-        stream = torch.cuda.current_stream().cuda_stream
+        stream = torch.cuda.current_stream(X.device).cuda_stream
     ws = None if workspace is None else workspace.data_ptr()
     _check(_lib.dense_dft_exec_inverse(plan.handle, X.data_ptr(), x.data_ptr(), ws, _vp(stream)),
            "dense_dft_exec_inverse")

@@ -154,3 +154,25 @@ def test_decimated_plan_rejects(N, p, want):
     h = ctypes.c_void_p(3)
     assert dd._lib.dense_dft_plan_decimated(ctypes.byref(h), N, p, 1.0, 1, dd.DD_C64, 0) == want
     assert not h.value
+
+
+def test_binding_checks_tensors_before_the_library():
+    """The binding refuses host tensors, wrong dtypes and short buffers with
+    DD_ERR_INVALID before any library call (the plan here has no handle, so
+    reaching the library would fail differently)."""
+    import torch
+    import paper_2403_16665_amd as dd
+    fake = dd.Plan(None, 1024, 4, 1.0, 3, dd.DD_C64, 0)
+    x = torch.zeros(3, 1024, dtype=torch.complex64)
+    X = torch.zeros(3, 4096, dtype=torch.complex64)
+    for call in (lambda: dd.dense_dft_exec(fake, x, X),
+                 lambda: fake.exec(x, out=X),
+                 lambda: dd.dense_dft_exec_inverse(fake, X, x),
+                 lambda: dd._one_desc((1024, 4, 1.0, dd.DD_C64, x[0], X[0])),
+                 lambda: dd._desc_array([(1024, 4, 1.0, dd.DD_C64, x[0], X[0])])):
+        with pytest.raises(dd.DenseDFTError) as e:
+            call()
+        assert e.value.status == 1 and "device" in str(e.value)
+    # a prepared dd_desc passes through unchanged
+    d = dd.dd_desc(1024, 4, 1.0, dd.DD_C64, 4096, 1 << 20)
+    assert dd._one_desc(d) is d

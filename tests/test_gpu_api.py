@@ -83,3 +83,30 @@ def test_submit_many_at_open_loop(oracle_mod):
     with pytest.raises(dd.DenseDFTError, match="queued 1 of 2"):
         dd.dense_dft_submit_many_at(srv, descs[:2], [now + 100_000, now])
     dd.dense_dft_server_destroy(srv)   # drains the queued request
+
+
+def test_binding_rejects_mismatched_device_tensors():
+    """Device tensors of the wrong dtype, too short, strided, or a workspace
+    smaller than the plan's: DD_ERR_INVALID from the binding, no launch."""
+    import torch
+    import paper_2403_16665_amd as dd
+    plan = dd.dense_dft_plan(65536, 8, 1.0, 2, dd.DD_C64)
+    x = torch.zeros(2, 65536, dtype=torch.complex64, device="cuda")
+    X = torch.zeros(2, 8 * 65536, dtype=torch.complex64, device="cuda")
+    ws_need = dd.dense_dft_workspace_size(plan)
+    assert ws_need > 0
+    bad = [lambda: dd.dense_dft_exec(plan, x.to(torch.complex128), X),
+           lambda: dd.dense_dft_exec(plan, x, X[:, :-1]),
+           lambda: dd.dense_dft_exec(plan, x[:1], X),
+           lambda: dd.dense_dft_exec(plan, torch.zeros(65536, 2, dtype=torch.complex64, device="cuda").t(), X),
+           lambda: dd.dense_dft_exec(plan, x, X, workspace=torch.empty(ws_need - 1, dtype=torch.uint8,
+                                                                         device="cuda")),
+           lambda: dd.dense_dft_exec_inverse(plan, X[:, :-8], x),
+           lambda: dd.dense_dft_exec_inverse(plan, X, x.real.contiguous())]
+    for i, call in enumerate(bad):
+        with pytest.raises(dd.DenseDFTError) as e:
+            call()
+        assert e.value.status == 1, i
+    # the exact buffers and a workspace of exactly the reported size are accepted
+    dd.dense_dft_exec(plan, x, X, workspace=torch.empty(ws_need, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
