@@ -103,7 +103,10 @@ typedef struct dd_plan *dd_plan_t;
  *   alpha  : dense sampling factor, integer >= 1 (alpha < 1 and non-integer
  *            alpha -> DD_ERR_UNSUPPORTED; alpha = 1/p has its own plan,
  *            dense_dft_plan_decimated).
- *   T      : finite, > 0.
+ *   T      : finite, > 0 (else DD_ERR_INVALID); T/N must be a normal number
+ *            in the arithmetic's precision (float for DD_F32 / DD_C64,
+ *            double otherwise), else DD_ERR_UNSUPPORTED: the kernels scale
+ *            every bin by it.
  *   batch  : number of signals, >= 1, batch*alpha*N must fit int64.
  *   dtype  : input dtype (see above).
  *   flags  : DD_TWIDDLE_FP64 or DD_TWIDDLE_FP32, optionally | DD_NO_WORKSPACE.
@@ -164,7 +167,9 @@ dd_status dense_dft_exec(dd_plan_t plan, const void *x, void *X,
  * Profiled launches (dense_dft_profile_begin) report kinds 4 (one pass),
  * 5 (pass A) and 6 (pass B).
  * Errors: DD_ERR_INVALID (null / misaligned / overlapping pointers),
- *         DD_ERR_DEVICE (kernel launch failed). */
+ *         DD_ERR_UNSUPPORTED (an alpha = 1/p plan, or 1/(alpha T) not a
+ *         normal number in the plan's precision), DD_ERR_DEVICE (kernel
+ *         launch failed). */
 dd_status dense_dft_exec_inverse(dd_plan_t plan, const void *X, void *x,
                                  void *workspace, void *stream);
 

@@ -300,6 +300,7 @@ dd_status plan_build(dd_plan_t* out, int64_t N, int32_t alpha, double T, int64_t
   const int64_t M = (int64_t)alpha * N;
   if (M > ((int64_t)1 << 31) || batch > INT64_MAX / M) return DD_ERR_UNSUPPORTED;
   if (!is_smooth(N)) return DD_ERR_UNSUPPORTED;
+  if (!scale_ok(T / (double)N, dtype == DD_F64 || dtype == DD_C128)) return DD_ERR_UNSUPPORTED;
 
   dd_plan* p = new (std::nothrow) dd_plan;
   if (!p) return DD_ERR_NOMEM;
@@ -706,6 +707,7 @@ dd_status dense_dft_exec(dd_plan_t p, const void* x, void* X, void* workspace, v
 dd_status dense_dft_exec_inverse(dd_plan_t p, const void* X, void* x, void* workspace, void* stream) {
   if (!p || !X || !x) return DD_ERR_INVALID;
   if (p->inner) return DD_ERR_UNSUPPORTED;  // alpha < 1 is a one-way transform (the fold loses information)
+  if (!scale_ok(1.0 / ((double)p->alpha * p->T), p->dbl)) return DD_ERR_UNSUPPORTED;
   const size_t cxb = cx_bytes(p);
   if ((uintptr_t)X % cxb != 0 || (uintptr_t)x % cxb != 0) return DD_ERR_INVALID;
   const size_t in_total = (size_t)p->batch * p->alpha * p->N * cxb;

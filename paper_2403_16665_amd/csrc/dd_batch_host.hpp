@@ -43,6 +43,7 @@ inline dd_status batch_check_shape(int64_t N, int alpha, double T, dd_dtype dtyp
   if (alpha < 1) return DD_ERR_UNSUPPORTED;
   if ((int64_t)alpha * N > ((int64_t)1 << 31)) return DD_ERR_UNSUPPORTED;
   if (!is_smooth(N)) return DD_ERR_UNSUPPORTED;
+  if (!scale_ok(T / (double)N, dtype == DD_F64 || dtype == DD_C128)) return DD_ERR_UNSUPPORTED;
   return DD_OK;
 }
 

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
+#include <cmath>
 #include <cstdint>
 
 #include "../../include/dense_dft.h"
@@ -22,6 +24,14 @@ inline bool is_smooth(int64_t n) {
   while (n % 3 == 0) n /= 3;
   while (n % 5 == 0) n /= 5;
   return n == 1;
+}
+
+// A factor the kernels scale by (T/N forward, 1/(alpha T) inverse) must be a
+// positive normal number in the arithmetic's precision (double, else float);
+// otherwise every bin would come out infinite, NaN or flushed to zero.
+inline bool scale_ok(double v, bool dbl) {
+  if (!std::isnormal(v) || v < 0.0) return false;
+  return dbl || (v >= (double)FLT_MIN && v <= (double)FLT_MAX);
 }
 
 inline int ilog2(int64_t v) {

@@ -53,6 +53,10 @@ def test_binding_loads_and_names_match():
     (1 << 24, 2, 1.0, 1, 2, 0, 2),           # double: 4096 x 4096 needs a column of 4096 in LDS
     (1 << 24, 2, 1.0, 1, 3, 0, 2),
     (1 << 20, 4096, 1.0, 1, 1, 0, 2),        # alpha*N > 2^31
+    (64, 2, 1e300, 1, 1, 0, 2),              # T/N beyond float: every bin would be infinite
+    (64, 2, 1e300, 1, 0, 0, 2),
+    (64, 2, 1e-40, 1, 1, 0, 2),              # T/N below float's normal range
+    (64, 2, 1e-310, 1, 3, 0, 2),             # T/N below double's normal range
 ])
 def test_plan_rejects_bad_arguments(N, alpha, T, batch, dtype, flags, want):
     import ctypes
@@ -141,7 +145,8 @@ def test_batch_plan_rejects_bad_descriptors():
                 dd.dd_desc(1024, 4, 1.0, dd.DD_C64, 4096, 4096 + 8)]:             # x and X overlap
         assert dd._lib.dense_dft_batch_plan(ctypes.byref(h), (dd.dd_desc * 1)(bad), 1, 0) == 1
     for bad in [dd.dd_desc(1024, 0, 1.0, dd.DD_C64, 4096, 1 << 20),               # alpha < 1
-                dd.dd_desc(7 * 64, 2, 1.0, dd.DD_C64, 4096, 1 << 20)]:            # prime factor 7
+                dd.dd_desc(7 * 64, 2, 1.0, dd.DD_C64, 4096, 1 << 20),             # prime factor 7
+                dd.dd_desc(1024, 4, 1e300, dd.DD_C64, 4096, 1 << 20)]:            # T/N beyond float
         assert dd._lib.dense_dft_batch_plan(ctypes.byref(h), (dd.dd_desc * 1)(bad), 1, 0) == 2
     assert dd._lib.dense_dft_batch_exec(None, None) == 1
     assert dd._lib.dense_dft_batch_destroy(None) == 1
