@@ -105,29 +105,46 @@ __device__ __forceinline__ void body_passA(const cx<R>* __restrict__ X, cx<R>* _
 #pragma unroll
   for (int u = 0; u < EPT; ++u)
     g[u] = mrow < rows ? load_once(xs + (int64_t)mrow + (int64_t)rows * (kb + u * TL)) : cx<R>{(R)0, (R)0};
+  // the inter-pass twiddle of this thread's row, W_{alpha N}^{m1 n2} =
+  // W_N^{k1 n2} W_{alpha N}^{j n2} with m1 = alpha k1 + j.  In single
+  // precision its loads go out with the gather, so one memory latency covers
+  // both, and only the product stays live through the FFT; in double the
+  // extra registers would spill, so they are loaded after the FFT.
+  constexpr bool EARLY = sizeof(R) == 4;
+  const int k1 = ok ? m1 / a.alpha : 0, j = ok ? m1 - k1 * a.alpha : 0;
+  const cx<R>* __restrict__ pw = a.twPost + (int64_t)k1 * L + t;
+  const cx<R>* __restrict__ q = a.twQ + (int64_t)j * L + t;
+  cx<R> w[EPT], wq[EPT];
+  if constexpr (EARLY) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) w[e] = pw[TL * e];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) wq[e] = q[TL * e];
+  }
 #pragma unroll
   for (int u = 0; u < EPT; ++u) ex[(kb + u * TL) * SR + rr] = g[u];
   __syncthreads();
   cx<R> v[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) v[e] = cconj(ex[(t + TL * e) * SR + r]);
+  if constexpr (EARLY) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) w[e] = cmul(w[e], wq[e]);
+  }
   __syncthreads();  // the staging area becomes the FFT's exchange buffer
   const RowLayout<L> lay(r);
   line_fft<R, L, (TL <= 64)>(v, t, ex, lay, a.twL);
   if (ok) {
-    // W_{alpha N}^{m1 n2} = W_N^{k1 n2} W_{alpha N}^{j n2}, m1 = alpha k1 + j
-    const int k1 = m1 / a.alpha, j = m1 - k1 * a.alpha;
-    const cx<R>* __restrict__ pw = a.twPost + (int64_t)k1 * L + t;
-    const cx<R>* __restrict__ q = a.twQ + (int64_t)j * L + t;
     cx<R>* gr = G + sig * a.y_stride + (int64_t)m1 * L + t;
-    // every twiddle load before the first store: loads and stores share one
-    // in-order completion counter, so a load issued after a store would wait
-    // for that store too
-    cx<R> w[EPT];
+    if constexpr (!EARLY) {
+      // every twiddle load before the first store: loads and stores share
+      // one in-order completion counter, so a load issued after a store
+      // would wait for that store too
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) w[e] = pw[TL * e];
+      for (int e = 0; e < EPT; ++e) w[e] = pw[TL * e];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) w[e] = cmul(w[e], q[TL * e]);
+      for (int e = 0; e < EPT; ++e) w[e] = cmul(w[e], q[TL * e]);
+    }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) gr[TL * e] = cmul(v[e], w[e]);
   }
