@@ -285,10 +285,15 @@ __device__ __forceinline__ void body_single_groups(const InAcc& x, cx<R>* __rest
 // traffic.)
 // HALF: the kernel may be given a.hrows > 0 (real input) and then stores
 // only the rows m1 < a.hrows; without it every row is stored.  A real
-// column's alpha-dense DFT is Hermitian, C[alpha N1 - m1] = conj(C[m1]), so
-// C_{alpha-j}[k1] = conj(C_j[N1 - 1 - k1]): when a block holds every j it
-// transforms only j <= alpha / 2 and takes the rows of alpha - j from the
-// transform of j, reversed through LDS.
+// column's alpha-dense DFT is Hermitian, C[alpha N1 - m1] = conj(C[m1]), with
+// alpha N1 - m1 = alpha (N1 - 1 - k1) + (alpha - j): when a block holds every
+// j it transforms only j <= alpha / 2 and also stores the rows of alpha - j.
+// The inter-pass twiddle of row alpha N1 - m1 is W_{N2}^{n2} times the
+// conjugate of that of m1, so Y[alpha N1 - m1][n2] = conj(Y[m1][n2]) W_{N2}^{n2}
+// and each thread stores those rows from its own values.  In double
+// precision and for lines of 5 * 2^a (20 elements per thread) that costs
+// occupancy or spills, so there the transform of j is reversed through LDS
+// and twiddled for the rows of alpha - j.
 template <typename R, class InAcc, int L, int C, bool HALF = false>
 __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y, const DenseArgs<R>& a,
                                            int64_t bid, unsigned char* smem, int tid) {
@@ -348,6 +353,13 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
   const unsigned out_step = (unsigned)(a.alpha * N2 * TL);
   cx<R>* ys = Y + sig * a.y_stride;
   const bool sym = HALF && a.hrows > 0 && a.njg == 1;
+  constexpr bool REG_MIRROR = HALF && sizeof(R) == 4 && L % 5 != 0;
+  // W_{N2}^{n2} = W_N^{N1 n2} (the mirror rows' factor), from rows 1 and
+  // N1 - 1 of the post-twiddle table; N1 = 1 takes it from W_{alpha N}^{j n2}
+  // W_{alpha N}^{(alpha - j) n2} in the loop
+  cx<R> wn2 = {(R)1, (R)0};
+  if constexpr (REG_MIRROR && L >= 2)
+    if (sym && colok) wn2 = cmul(a.twPost[N2 + n2], a.twPost[(L - 1) * N2 + n2]);
   for (int j = j0; j < j1; ++j) {
     if (sym && 2 * j > a.alpha) break;  // stored with their partners alpha - j
     cx<R> v[EPT];
@@ -369,11 +381,27 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
       cx<R>* yj = ys + (int64_t)j * N2;
       // rows kept: k1 < (hrows - j) / alpha, i.e. m1 = alpha k1 + j < hrows
       const int klim = HALF && a.hrows > 0 ? (a.hrows - j + a.alpha - 1) / a.alpha : L;
+      // real input, every j in the block: the rows of jd = alpha - j too, at
+      // k1' = N1 - 1 - k1 = (TL - 1 - t) + TL (EPT - 1 - e) (the primary
+      // store's form with lane offset alpha N2 (TL - 1 - t) + n2), kept
+      // while below hrows
+      const bool mir = REG_MIRROR && sym && j >= 1 && 2 * j < a.alpha;
+      const int jd = a.alpha - j;
+      cx<R>* yd = ys + (int64_t)jd * N2;
+      const unsigned off_d = (unsigned)(a.alpha * N2 * (TL - 1 - t) + n2);
+      const int klim_d = mir ? (a.hrows - jd + a.alpha - 1) / a.alpha : 0;
+      cx<R> w = wn2;
+      if constexpr (REG_MIRROR && L == 1)
+        if (mir) w = cmul(q, a.q_lds ? lds_read(qs + (jd - j0) * C + c) : a.twQ[jd * N2 + n2]);
 #pragma unroll
-      for (int e = 0; e < EPT; ++e)
-        if (!HALF || t + TL * e < klim) (yj + out_step * e)[out_off] = cmul(v[e], cmul(pw[e], q));
+      for (int e = 0; e < EPT; ++e) {
+        const cx<R> u = cmul(v[e], cmul(pw[e], q));
+        if (!HALF || t + TL * e < klim) (yj + out_step * e)[out_off] = u;
+        if constexpr (REG_MIRROR)
+          if (L - 1 - t - TL * e < klim_d) (yd + out_step * (EPT - 1 - e))[off_d] = cmul(cconj(u), w);
+      }
     }
-    if constexpr (HALF) {
+    if constexpr (HALF && !REG_MIRROR) {
       if (sym && j >= 1 && 2 * j < a.alpha) {
         const int jd = a.alpha - j;
         __syncthreads();  // the transform's last exchange has been read
