@@ -352,8 +352,13 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
   const unsigned out_off = (unsigned)(a.alpha * N2 * t + n2);  // lane part of (alpha k1 + j) N2 + n2
   const unsigned out_step = (unsigned)(a.alpha * N2 * TL);
   cx<R>* ys = Y + sig * a.y_stride;
-  const bool sym = HALF && a.hrows > 0 && a.njg == 1;
   constexpr bool REG_MIRROR = HALF && sizeof(R) == 4 && L % 5 != 0;
+  // SPLIT: with N1 and EPT even and hrows = alpha N1 / 2 + 1, every mirrored
+  // j keeps the rows k1 < N1 / 2 (elements e < EPT / 2) and its partner
+  // alpha - j the rows N1 - 1 - k1 < N1 / 2 (elements e >= EPT / 2): fixed
+  // element ranges, no per-lane predicates
+  constexpr bool SPLIT = REG_MIRROR && L % 2 == 0 && EPT % 2 == 0;
+  const bool sym = HALF && a.hrows > 0 && a.njg == 1 && (!SPLIT || a.hrows == a.alpha * L / 2 + 1);
   // W_{N2}^{n2} = W_N^{N1 n2} (the mirror rows' factor), from rows 1 and
   // N1 - 1 of the post-twiddle table; N1 = 1 takes it from W_{alpha N}^{j n2}
   // W_{alpha N}^{(alpha - j) n2} in the loop
@@ -393,12 +398,22 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
       cx<R> w = wn2;
       if constexpr (REG_MIRROR && L == 1)
         if (mir) w = cmul(q, a.q_lds ? lds_read(qs + (jd - j0) * C + c) : a.twQ[jd * N2 + n2]);
+      if (SPLIT && mir) {
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const cx<R> u = cmul(v[e], cmul(pw[e], q));
-        if (!HALF || t + TL * e < klim) (yj + out_step * e)[out_off] = u;
-        if constexpr (REG_MIRROR)
-          if (L - 1 - t - TL * e < klim_d) (yd + out_step * (EPT - 1 - e))[off_d] = cmul(cconj(u), w);
+        for (int e = 0; e < EPT / 2; ++e) (yj + out_step * e)[out_off] = cmul(v[e], cmul(pw[e], q));
+        // conj(v pw q) w = conj(v) conj(pw) (conj(q) w)
+        const cx<R> qw = cmul(cconj(q), w);
+#pragma unroll
+        for (int e = EPT / 2; e < EPT; ++e)
+          (yd + out_step * (EPT - 1 - e))[off_d] = cmul(cconj(v[e]), cmul(cconj(pw[e]), qw));
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const cx<R> u = cmul(v[e], cmul(pw[e], q));
+          if (!HALF || t + TL * e < klim) (yj + out_step * e)[out_off] = u;
+          if constexpr (REG_MIRROR && !SPLIT)
+            if (L - 1 - t - TL * e < klim_d) (yd + out_step * (EPT - 1 - e))[off_d] = cmul(cconj(u), w);
+        }
       }
     }
     if constexpr (HALF && !REG_MIRROR) {
