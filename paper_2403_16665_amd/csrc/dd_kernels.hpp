@@ -384,6 +384,8 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
     if (colok) {
       const cx<R> q = a.q_lds ? lds_read(qs + (j - j0) * C + c) : a.twQ[j * N2 + n2];  // W_{alpha N}^{j n2}
       cx<R>* yj = ys + (int64_t)j * N2;
+      unsigned out_off_j = out_off;
+      if constexpr (REG_MIRROR) asm volatile("" : "+v"(out_off_j));
       // rows kept: k1 < (hrows - j) / alpha, i.e. m1 = alpha k1 + j < hrows
       const int klim = HALF && a.hrows > 0 ? (a.hrows - j + a.alpha - 1) / a.alpha : L;
       // real input, every j in the block: the rows of jd = alpha - j too, at
@@ -393,14 +395,15 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
       const bool mir = REG_MIRROR && sym && j >= 1 && 2 * j < a.alpha;
       const int jd = a.alpha - j;
       cx<R>* yd = ys + (int64_t)jd * N2;
-      const unsigned off_d = (unsigned)(a.alpha * N2 * (TL - 1 - t) + n2);
+      unsigned off_d = (unsigned)(a.alpha * N2 * (TL - 1 - t) + n2);
+      if constexpr (REG_MIRROR) asm volatile("" : "+v"(off_d));
       const int klim_d = mir ? (a.hrows - jd + a.alpha - 1) / a.alpha : 0;
       cx<R> w = wn2;
       if constexpr (REG_MIRROR && L == 1)
         if (mir) w = cmul(q, a.q_lds ? lds_read(qs + (jd - j0) * C + c) : a.twQ[jd * N2 + n2]);
       if (SPLIT && mir) {
 #pragma unroll
-        for (int e = 0; e < EPT / 2; ++e) (yj + out_step * e)[out_off] = cmul(v[e], cmul(pw[e], q));
+        for (int e = 0; e < EPT / 2; ++e) (yj + out_step * e)[out_off_j] = cmul(v[e], cmul(pw[e], q));
         // conj(v pw q) w = conj(v) conj(pw) (conj(q) w)
         const cx<R> qw = cmul(cconj(q), w);
 #pragma unroll
@@ -410,7 +413,7 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
           const cx<R> u = cmul(v[e], cmul(pw[e], q));
-          if (!HALF || t + TL * e < klim) (yj + out_step * e)[out_off] = u;
+          if (!HALF || t + TL * e < klim) (yj + out_step * e)[out_off_j] = u;
           if constexpr (REG_MIRROR && !SPLIT)
             if (L - 1 - t - TL * e < klim_d) (yd + out_step * (EPT - 1 - e))[off_d] = cmul(cconj(u), w);
         }
