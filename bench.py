@@ -34,10 +34,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 
-# Sources that fix the launches of a plain transform (kernels, launch
-# geometry, planner and tuner): the counter summary is void once any changes.
+# Sources that fix the launches of the plain forward and inverse transforms
+# (kernels, launch geometry, planner and tuner): the counter summaries are
+# void once any changes.
 TRAFFIC_SOURCES = ("dd_fft.hpp", "dd_kernels.hpp", "dd_inst.hpp", "dd_launch.hpp", "dd_host.hpp",
-                   "dd_pass_f32.hip", "dd_single_f32.hip", "dd_misc.hip", "dd_api.cpp", "dd_tune.cpp")
+                   "dd_pass_f32.hip", "dd_single_f32.hip", "dd_misc.hip", "dd_api.cpp", "dd_tune.cpp",
+                   "dd_inverse.hpp", "dd_inv_f32.hip")
 
 
 def kernel_source_hash():
@@ -439,8 +441,12 @@ def run_inverse(args):
     T, M = N * dt, alpha * N
     x = np.stack([siggen.tones_complex(g, N, dt) for g in siggen.rngs(1, batch)])
     xd = torch.from_numpy(x).cuda()
-    if args.tune:
+    if args.tune_db and os.path.exists(args.tune_db):
+        dd.dense_dft_tune_load(args.tune_db)  # the schedule of an earlier run, no tuner launches
+    elif args.tune:
         dd.dense_dft_tune(N, alpha, batch, dd.DD_C64)
+        if args.tune_db:
+            dd.dense_dft_tune_save(args.tune_db)
     plan = dd.dense_dft_plan(N, alpha, T, batch, dd.DD_C64)
     X = torch.empty(batch, M, dtype=torch.complex64, device="cuda")
     dd.dense_dft_exec(plan, xd, X)
@@ -469,6 +475,7 @@ def run_inverse(args):
     rt = float((back - xd).abs().pow(2).sum().sqrt() / xd.abs().pow(2).sum().sqrt())
     b_alg = batch * (M * 8 + N * 8)
     achieved = b_alg / (kms * 1e-3) / 1e9
+    traffic = measured_traffic("inverse")
     print(json.dumps({
         "metric": "dense-spectrum bins/s & % HBM peak, batched vs plain at rel L2<=1e-5; p50/p99",
         "value": batch * M / (ms * 1e-3), "unit": "bins/s", "n_gpus": 1, "steps": args.steps,
@@ -479,7 +486,8 @@ def run_inverse(args):
         "kernels": kernels,
         "round_trip_rel_l2": rt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "amplification": traffic / b_alg if traffic else None,
                      "what": "inverse transform per step: algorithmic bytes batch*(alpha*N*8 + N*8) / summed "
                              "kernel durations"},
     }), flush=True)
