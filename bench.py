@@ -35,11 +35,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 
 # Sources that fix the launches of the plain forward and inverse transforms
-# (kernels, launch geometry, planner and tuner): the counter summaries are
-# void once any changes.
+# and of the persistent batch (kernels, launch geometry, planner and tuner):
+# the counter summaries are void once any changes.
 TRAFFIC_SOURCES = ("dd_fft.hpp", "dd_kernels.hpp", "dd_inst.hpp", "dd_launch.hpp", "dd_host.hpp",
                    "dd_pass_f32.hip", "dd_single_f32.hip", "dd_misc.hip", "dd_api.cpp", "dd_tune.cpp",
-                   "dd_inverse.hpp", "dd_inv_f32.hip")
+                   "dd_inverse.hpp", "dd_inv_f32.hip",
+                   "dd_batch.hip", "dd_batch.hpp", "dd_batch_host.hpp", "dd_batch_api.cpp")
 
 
 def kernel_source_hash():
@@ -195,7 +196,14 @@ def run_uneven(args):
     xs = [torch.from_numpy(x).cuda() for x in xs_np]
     Xs = [torch.empty(a * N, dtype=torch.complex64, device="cuda") for (N, a) in mix]
     descs = [(N, a, N * dt, dd.DD_C64, xs[i], Xs[i]) for i, (N, a) in enumerate(mix)]
-    tuning = tune_classes(dd, mix) if args.tune else None
+    tuning = None
+    if args.tune_db and os.path.exists(args.tune_db):
+        dd.dense_dft_tune_load(args.tune_db)  # the schedules of an earlier run, no tuner launches
+        tuning = {"loaded": args.tune_db}
+    elif args.tune:
+        tuning = tune_classes(dd, mix)
+        if args.tune_db:
+            dd.dense_dft_tune_save(args.tune_db)
     b = dd.dense_dft_batch_plan(descs)
     tasks, grid, scratch, fb = dd.dense_dft_batch_info(b)
     plans = [dd.dense_dft_plan(N, a, N * dt, 1, dd.DD_C64) for (N, a) in mix]
@@ -557,8 +565,9 @@ def main():
                     help="serving: Poisson arrival rates (requests/s)")
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests per rate")
     ap.add_argument("--tune-db", default="", metavar="PATH",
-                    help="default-shape workloads: load the tuning table from PATH if it exists, "
-                         "else tune and save it there (profiling runs then time the same schedule)")
+                    help="default, real-input, inverse and uneven workloads: load the tuning table "
+                         "from PATH if it exists, else tune and save it there (profiling runs then "
+                         "time the same schedules)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="instead of the transform, run --steps plain device copies of MIB MiB "
                          "(calibrates the profiler's HBM byte counters)")
