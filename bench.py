@@ -257,6 +257,8 @@ def run_uneven(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("uneven"),
                      "what": "whole batch per step: algorithmic bytes sum(N*8 + alpha*N*8) / step time"},
     }
+    if result["roofline"]["traffic"]:
+        result["roofline"]["amplification"] = result["roofline"]["traffic"] / b_alg
     if not args.no_cpu:
         N0, a0 = mix[0]
         samples, cpu = cpu_baseline([xs_np[0]], a0, N0 * dt, a0 * N0, N0)
