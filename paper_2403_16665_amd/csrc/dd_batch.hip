@@ -1,4 +1,6 @@
 // dd_batch.hip -- the persistent batch kernel and its launchers.
+#include <mutex>
+
 #include "dd_batch.hpp"
 #include "dd_launch.hpp"
 
@@ -165,14 +167,28 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_second(const BatchItem*
 
 hipError_t batch_set_lds(size_t lds1, size_t lds2) {
   // dynamic LDS plus the kernels' static word beyond the default 64 KiB
-  // needs the attribute; it is set outside any stream capture
-  hipError_t e = hipSuccess;
-  if (lds1 + 64 > 64 * 1024)
+  // needs the attribute; it is set outside any stream capture.  The limits
+  // only ever rise: a server's captured graphs launch with the largest
+  // sizes, and a batch plan or tuner run made beside it must not lower them.
+  // Tracked per device (the attribute is set on the current one).
+  constexpr int MAXDEV = 64;
+  static std::mutex mu;
+  static size_t cur1[MAXDEV] = {}, cur2[MAXDEV] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (lds1 + 64 > 64 * 1024 && lds1 > cur1[dev]) {
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_first), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds1);
-  if (e == hipSuccess && lds2 + 64 > 64 * 1024)
+    if (e == hipSuccess) cur1[dev] = lds1;
+  }
+  if (e == hipSuccess && lds2 + 64 > 64 * 1024 && lds2 > cur2[dev]) {
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_second),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+    if (e == hipSuccess) cur2[dev] = lds2;
+  }
   return e;
 }
 

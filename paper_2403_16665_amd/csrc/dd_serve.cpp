@@ -179,7 +179,10 @@ bool launch_slot(dd_server* s, Slot& slot, std::unique_lock<std::mutex>& lk) {
       const ClassTables* ct = nullptr;
       st = class_tables(s, r->d, r->sc, &ct);
       if (st == DD_OK) {
-        cx<float>* Y = r->sc.single ? nullptr : reinterpret_cast<cx<float>*>(s->pool + r->scratch_off);
+        // the schedule is the class's, fixed when its tables were made (the
+        // tuning table may have changed since the request was classified);
+        // every request reserves one spectrum of scratch, enough for either
+        cx<float>* Y = ct->sc.single ? nullptr : reinterpret_cast<cx<float>*>(s->pool + r->scratch_off);
         fill_item(slot.tab.items()[i], r->d, *ct, Y);
       }
     }

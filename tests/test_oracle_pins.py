@@ -346,6 +346,25 @@ def test_inverse_single_bin_closed_form(oracle_mod):
     assert rel(oracle_mod.inverse_alpha_dft(X, alpha, T), ref) < TOL
 
 
+def test_inverse_large_M_direct_sincos_path(oracle_mod):
+    """alpha N above the oracle's table limit (2^22): the inverse takes the
+    direct libm path.  The spectrum is numpy's FFT of the zero-padded signal
+    (the forward transform, Section 4's zero-padding identity), so the
+    inverse must return x_n for n < N and zero for N <= n < alpha N; each
+    sampled value is also (N/T) ifft(X)_n of the same spectrum."""
+    rng = np.random.default_rng(17)
+    N, alpha, T = 1 << 17, 64, 3.0     # M = 2^23
+    x = rand_c(rng, N)
+    X = np.fft.fft(np.concatenate([x, np.zeros((alpha - 1) * N)])) * (T / N)
+    n_lo = np.sort(rng.choice(N, 12, replace=False))
+    n_hi = N + np.sort(rng.choice((alpha - 1) * N, 12, replace=False))
+    got = oracle_mod.inverse_alpha_dft_samples(X, alpha, T, np.concatenate([n_lo, n_hi]))
+    assert rel(got[:12], x[n_lo]) < 1e-11
+    assert np.max(np.abs(got[12:])) < 1e-11 * np.max(np.abs(x[n_lo]))
+    ref = np.fft.ifft(X) * (N / T)
+    assert rel(got, ref[np.concatenate([n_lo, n_hi])]) < 1e-10
+
+
 @pytest.mark.parametrize("mutation", [1, 2, 3, 4])
 def test_inverse_pins_reject_planted_mistakes(oracle_mod, mutation):
     """Each planted mistake of the inverse fails at least one of the pins above."""
