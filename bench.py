@@ -1,22 +1,24 @@
 """Throughput benchmark of the alpha-dense DFT on one MI355X.
 
-Default workload: 256 complex64 signals, N = 65536 samples at dt = 1e-3 s
-(T = 65.536 s), alpha = 8 -> 524288 bins per signal; each signal is 5 unit
-complex tones at uniform random frequencies and phases plus complex Gaussian
-noise (sigma = 0.05), seeded.  One step = one dense_dft_exec over the whole
-batch, inputs resident in HBM.
+Default workload (headline): the metric's own comparison, batched vs plain.
+  * value: 1000 complex64 signals of uneven N (log-uniform over 2^8..2^18,
+    with 3*2^k and 5*2^k) and alpha in {2, 3, 4, 8, 16}, tone-plus-noise,
+    transformed in one persistent batch launch; output bins/s, against the
+    same 1000 signals as 1000 plain executions (`plain`, `batched_over_plain`);
+    rel. L2 against the FP64 oracle on seeded bins of 32 random signals, whose
+    timing is the cpu_baseline; roofline of the whole batch per step.
+  * plain_kernel_256x65536_a8: the plain kernel on 256 complex64 signals,
+    N = 65536, alpha = 8 (524288 bins each), with its per-kernel HIP-event
+    durations and roofline.
+  * serving: Poisson request streams (1k, 10k, 50k requests/s) through the
+    request server, batched vs plain per-request execution, p50/p99 latency.
+Inputs are resident in HBM when the timed region starts.  Prints ONE JSON line.
 
-Prints ONE JSON line: bins/s, per-kernel HIP-event durations, the HBM
-roofline of the transform (algorithmic bytes = N*8 + alpha*N*8 per signal),
-the rel. L2 error of the timed output against the FP64 oracle on a bin
-sample, and the oracle's own rate on the host cores (cpu_baseline).
-
-Other workloads (--workload): precision (1 x 2^22, alpha 16, c64),
-plain_f64 (1 x 1024, alpha 4, real float64), uneven (1000 signals of uneven N
-and alpha in one persistent launch vs 1000 plain launches) and serving
-(Poisson request streams through the request server, batched vs plain,
-p50/p99 latency) and ablation (the default shape against the FFT of the
-zero-padded signals, by this library and by the platform FFT library).
+Other workloads (--workload): batch_c64 (the plain kernel alone, with the
+oracle's CPU rate), real_f32, precision (1 x 2^22, alpha 16, c64, FP64 vs
+FP32 twiddles), plain_f64 (1 x 1024, alpha 4, real float64), uneven,
+serving (a full rate sweep), ablation (the FFT of the zero-padded signals),
+inverse and decimated (alpha = 1/p).
 """
 from __future__ import annotations
 
@@ -32,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+METRIC = "dense-spectrum bins/s & % HBM peak, batched vs plain at rel L2<=1e-5; p50/p99"
 
 
 # Sources that fix the launches of the plain forward and inverse transforms
@@ -68,6 +71,7 @@ def measured_traffic(workload):
     return None
 
 WORKLOADS = {
+    "headline": dict(batch=0, N=0, alpha=0, dt=1e-3, input="uneven batch + plain kernel + serving"),
     "batch_c64": dict(batch=256, N=65536, alpha=8, dt=1e-3, input="complex64"),
     "real_f32": dict(batch=256, N=65536, alpha=8, dt=1e-3, input="float32 real"),
     "precision": dict(batch=1, N=1 << 22, alpha=16, dt=1e-3, input="complex64"),
@@ -135,10 +139,27 @@ def precision_errors(dd, xd, Xd, N, alpha, T):
     dd.dense_dft_exec(p32, xd, X32)
     torch.cuda.synchronize()
     out = {"bins": int(len(bins)), "bound": 1e-5, "reference": "FP64 oracle, " + os.path.relpath(path, ROOT)}
-    for name, X in (("rel_l2_fp64_twiddles", Xd), ("rel_l2_fp32_twiddles", X32)):
+    # the whole spectrum's RMS, (T/N) |x|_2 by Parseval: the sampled error
+    # over it estimates the relative L2 error of all alpha*N bins
+    xs = xd[0].to(torch.complex128)
+    rms = T / N * float(xs.abs().pow(2).sum().sqrt())
+    for tag, X in (("fp64_twiddles", Xd), ("fp32_twiddles", X32)):
         got = X[0][idx].cpu().numpy()
-        out[name] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        out["rel_l2_" + tag] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        out["rms_rel_" + tag] = float(np.sqrt(np.mean(np.abs(got - ref) ** 2)) / rms)
+    out["fp32_over_fp64"] = {"subset": out["rel_l2_fp32_twiddles"] / out["rel_l2_fp64_twiddles"],
+                             "rms": out["rms_rel_fp32_twiddles"] / out["rms_rel_fp64_twiddles"]}
     return out
+
+
+def parse_sched(text):
+    """'N1xN2[:JGROUP[:CHUNK]]' -> the library's two-pass schedule record."""
+    import paper_2403_16665_amd as dd
+    parts = text.split(":")
+    n1, n2 = (int(v) for v in parts[0].lower().split("x"))
+    jg = int(parts[1]) if len(parts) > 1 else 0
+    chunk = int(parts[2]) if len(parts) > 2 else 0
+    return dd.make_sched(2, N1=n1, N2=n2, jgroup=jg, chunk=chunk)
 
 
 def cpu_model() -> str:
@@ -183,9 +204,45 @@ def cpu_baseline(x_rows, alpha, T, M, N, target_s=20.0):
                                f"multiply-adds, FP64 direct sum), {el:.1f} s"}
 
 
-def run_uneven(args):
+def uneven_oracle_check(xs_np, mix, Xs, dt, nsig=32, nbins=2048, seed=321):
+    """rel L2 of the batched output against the FP64 oracle on seeded bins of
+    `nsig` randomly drawn signals of the uneven mix (all bins when a spectrum
+    has no more than `nbins`), timed: the oracle's rate on this sample is the
+    workload's cpu_baseline."""
+    import oracle
+    import siggen
+    rng = np.random.default_rng(seed)
+    pick = np.sort(rng.choice(len(mix), size=min(nsig, len(mix)), replace=False))
+    num = den = 0.0
+    done, el, macs = 0, 0.0, 0
+    worst = 0.0
+    for i in pick:
+        N, a = mix[int(i)]
+        bins = siggen.bin_subset(rng, a * N, nbins)
+        t0 = time.perf_counter()
+        ref = oracle.alpha_dft_bins(xs_np[int(i)], a, N * dt, bins)
+        el += time.perf_counter() - t0
+        got = Xs[int(i)].cpu().numpy()[bins]
+        e2 = float(np.sum(np.abs(got - ref) ** 2))
+        r2 = float(np.sum(np.abs(ref) ** 2))
+        worst = max(worst, float(np.sqrt(e2 / r2)))
+        num += e2
+        den += r2
+        done += len(bins)
+        macs += len(bins) * N
+    check = {"signals": int(len(pick)), "bins": done, "rel_l2": float(np.sqrt(num / den)),
+             "max_rel_l2_per_signal": worst}
+    cpu = {"value": done / el, "unit": "bins/s", "cores": oracle.threads(), "cpu_model": cpu_model(),
+           "kind": "oracle",
+           "sample": f"{done} seeded bins of {len(pick)} randomly drawn signals of the 1000-signal mix "
+                     f"({macs / 1e9:.2f} G complex multiply-adds, FP64 direct sum), {el:.1f} s"}
+    return check, cpu
+
+
+def run_uneven(args, tuned=False):
     """1000 complex64 signals, (N, alpha) drawn log-uniformly (siggen.uneven_mix),
-    tone-plus-noise content: one persistent batch launch vs 1000 plain launches."""
+    tone-plus-noise content: one persistent batch launch vs 1000 plain launches.
+    Returns the record (tuned: the caller has already tuned every class)."""
     import torch
     import paper_2403_16665_amd as dd
     import siggen
@@ -200,6 +257,8 @@ def run_uneven(args):
     if args.tune_db and os.path.exists(args.tune_db):
         dd.dense_dft_tune_load(args.tune_db)  # the schedules of an earlier run, no tuner launches
         tuning = {"loaded": args.tune_db}
+    elif tuned:
+        tuning = {"classes": "tuned before this record"}
     elif args.tune:
         tuning = tune_classes(dd, mix)
         if args.tune_db:
@@ -231,68 +290,85 @@ def run_uneven(args):
 
     ms_b, wall_b = timed(lambda: dd.dense_dft_batch_exec(b, stream=sp), args.steps, args.warmup)
     assert dd.dense_dft_batch_status(b) == 0
+    # per-step device times of the batch (p50 / p99), one event pair per step
+    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+    for e0, e1 in step_ev:
+        e0.record(stream)
+        dd.dense_dft_batch_exec(b, stream=sp)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    step_ms = np.array([e0.elapsed_time(e1) for e0, e1 in step_ev])
     Xb = [X.clone() for X in Xs[:50]]
     ms_p, wall_p = timed(plain, max(3, args.steps // 10), max(1, args.warmup // 5))
     torch.cuda.synchronize()
     same = all(torch.allclose(a_, c_, rtol=0, atol=1e-5 * float(c_.abs().max()))
                for a_, c_ in zip(Xb, Xs[:50]))
+    # the batched outputs again, for the oracle check
+    dd.dense_dft_batch_exec(b, stream=sp)
+    torch.cuda.synchronize()
     achieved = b_alg / (ms_b * 1e-3) / 1e9
     result = {
-        "metric": "dense-spectrum bins/s & % HBM peak, batched vs plain at rel L2<=1e-5; p50/p99",
+        "metric": METRIC,
         "value": bins / (ms_b * 1e-3), "unit": "bins/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_b, "wall_ms_per_step": wall_b,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "uneven", "signals": len(mix), "bins_per_step": bins,
+        "config": {"workload": "uneven: 1000 complex64 signals, N log-uniform over 2^8..2^18 "
+                               "(with 3*2^k, 5*2^k), alpha in {2,3,4,8,16}, one persistent batch",
+                   "signals": len(mix), "bins_per_step": bins,
                    "N_range": [min(n for n, _ in mix), max(n for n, _ in mix)],
                    "alphas": sorted(set(a for _, a in mix)), "input": "complex64", "dt": dt},
+        "step_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "batch": {"tasks": tasks, "grid": grid, "scratch_bytes": scratch, "fallback_signals": fb,
                   "launches_per_step": "1 staging kernel + 1 or 2 queue kernels"},
         "plain": {"value": bins / (ms_p * 1e-3), "ms_per_step": ms_p, "wall_ms_per_step": wall_p,
-                  "launches_per_step": "1000 execs"},
+                  "launches_per_step": "1000 execs (resident plans, one stream)"},
         "batched_over_plain": ms_p / ms_b,
         "tuning": tuning,
         "batched_equals_plain": bool(same),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("uneven"),
-                     "what": "whole batch per step: algorithmic bytes sum(N*8 + alpha*N*8) / step time"},
+                     "what": "whole batch per step (staging + two queue kernels): algorithmic bytes "
+                             "sum(N*8 + alpha*N*8) / step time"},
     }
     if result["roofline"]["traffic"]:
         result["roofline"]["amplification"] = result["roofline"]["traffic"] / b_alg
     if not args.no_cpu:
-        N0, a0 = mix[0]
-        samples, cpu = cpu_baseline([xs_np[0]], a0, N0 * dt, a0 * N0, N0)
-        _, bins0, ref = samples[0]
-        got = Xs[0].cpu().numpy()[bins0]
-        result["rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        check, cpu = uneven_oracle_check(xs_np, mix, Xs, dt)
+        result["rel_l2"] = check["rel_l2"]
+        result["oracle_check"] = check
         result["cpu_baseline"] = cpu
-    print(json.dumps(result), flush=True)
+    del b, plans
+    return result
 
 
-def run_serving(args):
+def run_serving(args, rates=None, counts=None, tuned=False):
     """Open-loop Poisson request streams through the request server, batched
     (continuous batching, one persistent launch per batch) and plain (every
     request alone as one plain execution).  (N, alpha) as the uneven mix,
     float32 real or complex64 input half and half, tone-plus-noise content,
-    inputs resident in HBM before the stream starts."""
-    import ctypes
+    inputs resident in HBM before the stream starts.  `counts[i]` requests at
+    `rates[i]`.  Returns the record."""
     import torch
     import paper_2403_16665_amd as dd
     import siggen
     dt = 1e-3
-    rates = [float(r) for r in args.rates.split(",")]
-    count = args.requests
+    rates = rates or [float(r) for r in args.rates.split(",")]
+    counts = counts or [args.requests] * len(rates)
+    count = max(counts)
     rng = siggen.rngs(5, 1)[0]
     mix = siggen.uneven_mix(rng, count)
     codes = [dd.DD_F32 if u < 0.5 else dd.DD_C64 for u in rng.random(count)]
     # one input per (N, dtype): requests read it, each writes its own output
-    inputs = {}
+    inputs, inputs_np = {}, {}
     kinds = sorted(set((N, c) for (N, _), c in zip(mix, codes)))
     for g, (N, c) in zip(siggen.rngs(6, len(kinds)), kinds):
         if c == dd.DD_F32:
-            inputs[(N, c)] = torch.from_numpy(siggen.tones_real(g, N, dt, 1)[0].astype(np.float32)).cuda()
+            inputs_np[(N, c)] = siggen.tones_real(g, N, dt, 1)[0].astype(np.float32)
         else:
-            inputs[(N, c)] = torch.from_numpy(siggen.tones_complex(g, N, dt)).cuda()
+            inputs_np[(N, c)] = siggen.tones_complex(g, N, dt)
+        inputs[(N, c)] = torch.from_numpy(inputs_np[(N, c)]).cuda()
     offs = np.concatenate([[0], np.cumsum([a * N for N, a in mix])])
     arena = torch.empty(int(offs[-1]), dtype=torch.complex64, device="cuda")
     torch.cuda.synchronize()
@@ -303,59 +379,71 @@ def run_serving(args):
                     dtype=np.float64)
     budget = 16 << 30
 
-    def stream_through(server, rate, seed):
-        arr = siggen.poisson_arrivals(np.random.default_rng(seed), rate, count)
+    def stream_through(server, rate, n, seed):
+        arr = siggen.poisson_arrivals(np.random.default_rng(seed), rate, n)
         t0 = dd.dense_dft_clock_ns() + 2_000_000
         due = [t0 + int(a_ * 1e9) for a_ in arr]
-        tickets = dd.dense_dft_submit_many_at(server, descs, due)   # native open-loop generator
+        tickets = dd.dense_dft_submit_many_at(server, descs[:n], due)   # native open-loop generator
         res = [dd.dense_dft_wait(server, int(tk), 120_000_000) for tk in tickets]
         assert all(r["status"] == 0 for r in res)
         lat = np.array([r["t_done_ns"] - r["t_arrival_ns"] for r in res]) / 1e6
         span = (max(r["t_done_ns"] for r in res) - min(r["t_arrival_ns"] for r in res)) / 1e9
-        return {"rate_req_s": rate, "requests": count, "bins_per_s": float(bins.sum() / span),
-                "hbm_GBps": float(balg.sum() / span / 1e9), "p50_ms": float(np.percentile(lat, 50)),
-                "p99_ms": float(np.percentile(lat, 99)), "mean_batch": float(np.mean([r["batch_requests"] for r in res]))}
+        return {"rate_req_s": rate, "requests": n, "bins_per_s": float(bins[:n].sum() / span),
+                "hbm_GBps": float(balg[:n].sum() / span / 1e9), "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)),
+                "mean_batch": float(np.mean([r["batch_requests"] for r in res]))}
 
-    tuning = tune_classes(dd, mix, dtypes=(dd.DD_C64, dd.DD_F32)) if args.tune else None
+    if tuned:
+        tuning = {"classes": "tuned before this record"}
+    else:
+        tuning = tune_classes(dd, mix, dtypes=(dd.DD_C64, dd.DD_F32)) if args.tune else None
     out = {}
     for mode, name in ((dd.DD_SERVE_PLAIN, "plain"), (dd.DD_SERVE_BATCHED, "batched")):
         srv = dd.dense_dft_server_create(mode=mode, hbm_budget_bytes=budget)
         for (N, a), c in sorted(set(zip(mix, codes))):
             dd.dense_dft_server_warm(srv, N, a, N * dt, c)
-        stream_through(srv, rates[-1], 99)         # warm-up pass over every class
-        out[name] = [stream_through(srv, r, 100 + k) for k, r in enumerate(rates)]
+        stream_through(srv, rates[-1], min(count, 4000), 99)      # warm-up pass over the stream
+        out[name] = [stream_through(srv, r, n, 100 + k) for k, (r, n) in enumerate(zip(rates, counts))]
         out[name + "_stats"] = dd.dense_dft_server_stats(srv)
         dd.dense_dft_server_destroy(srv)
-    # the arena holds the batched pass's outputs: 1% of the requests again
-    # through a plain plan, compared by relative L2 over the whole spectrum
-    checked, worst = 0, 0.0
-    for i in range(0, count, 100):
-        N, a = mix[i]
-        c = codes[i]
-        ref = dd.alpha_dft(inputs[(N, c)], a, N * dt)
-        got = arena[int(offs[i]):int(offs[i + 1])]
-        torch.cuda.synchronize()
-        worst = max(worst, float((got - ref).abs().pow(2).sum().sqrt() / ref.abs().pow(2).sum().sqrt()))
-        checked += 1
+    out["batched_p99_le_plain"] = [b["p99_ms"] <= p["p99_ms"] for p, b in zip(out["plain"], out["batched"])]
+    # the arena holds the batched pass's outputs of the last rate: 1% of its
+    # requests against the FP64 oracle on seeded bins
+    import oracle
+    crng = np.random.default_rng(77)
+    n_last = counts[-1]
+    pick = np.sort(crng.choice(n_last, size=max(1, n_last // 100), replace=False))
+    num = den = 0.0
+    for i in pick:
+        N, a = mix[int(i)]
+        c = codes[int(i)]
+        b_ = siggen.bin_subset(crng, a * N, 512)
+        ref = oracle.alpha_dft_bins(inputs_np[(N, c)], a, N * dt, b_)
+        got = arena[int(offs[i]):int(offs[i + 1])].cpu().numpy()[b_]
+        num += float(np.sum(np.abs(got - ref) ** 2))
+        den += float(np.sum(np.abs(ref) ** 2))
     top = out["batched"][-1]
     result = {
-        "metric": "dense-spectrum bins/s & % HBM peak, batched vs plain at rel L2<=1e-5; p50/p99",
-        "value": top["bins_per_s"], "unit": "bins/s", "n_gpus": 1, "steps": count, "warmup": count,
+        "metric": METRIC,
+        "value": top["bins_per_s"], "unit": "bins/s", "n_gpus": 1, "steps": counts[-1], "warmup": min(count, 4000),
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "serving", "requests_per_rate": count, "rates_req_s": rates,
+        "config": {"workload": "serving: Poisson request streams, N and alpha as the uneven mix, "
+                               "float32 real / complex64 input 1:1",
+                   "requests_per_rate": counts, "rates_req_s": rates,
                    "N_range": [min(n for n, _ in mix), max(n for n, _ in mix)], "alphas": [2, 3, 4, 8, 16],
-                   "inputs": "float32 real / complex64, 1:1", "hbm_budget_bytes": budget},
+                   "hbm_budget_bytes": budget},
         "serving": out,
         "tuning": tuning,
         "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
-        "plain_at_top_rate": out["plain"][-1],
-        "check": {"requests": checked, "max_rel_l2_vs_plain": worst, "bound": 1e-5},
+        "oracle_check": {"requests": int(len(pick)), "bins_each": 512, "rel_l2": float(np.sqrt(num / den)),
+                         "bound": 1e-5, "rate_req_s": rates[-1]},
         "roofline": {"bound": "hbm", "achieved": top["hbm_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": top["hbm_GBps"] / HBM_PEAK_GBS, "traffic": None,
                      "what": "served algorithmic bytes sum(N*s_in + alpha*N*8) / wall span at the top rate"},
     }
-    print(json.dumps(result), flush=True)
+    del arena
+    return result
 
 
 def run_ablation(args):
@@ -416,7 +504,7 @@ def run_ablation(args):
     b_a = batch * (N * 8 + M * 8)
     b_pad = batch * (M * 8 + M * 8)
     res = {
-        "metric": "dense-spectrum bins/s & % HBM peak, batched vs plain at rel L2<=1e-5; p50/p99",
+        "metric": METRIC,
         "value": bins / (ms_a * 1e-3), "unit": "bins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_a, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
@@ -437,7 +525,7 @@ def run_ablation(args):
                      "frac": b_a / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "what": "alpha-dense transform, end to end per step"},
     }
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def run_inverse(args):
@@ -486,8 +574,8 @@ def run_inverse(args):
     b_alg = batch * (M * 8 + N * 8)
     achieved = b_alg / (kms * 1e-3) / 1e9
     traffic = measured_traffic("inverse")
-    print(json.dumps({
-        "metric": "dense-spectrum bins/s & % HBM peak, batched vs plain at rel L2<=1e-5; p50/p99",
+    return {
+        "metric": METRIC,
         "value": batch * M / (ms * 1e-3), "unit": "bins/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -500,7 +588,7 @@ def run_inverse(args):
                      "amplification": traffic / b_alg if traffic else None,
                      "what": "inverse transform per step: algorithmic bytes batch*(alpha*N*8 + N*8) / summed "
                              "kernel durations"},
-    }), flush=True)
+    }
 
 
 def run_decimated(args):
@@ -530,14 +618,36 @@ def run_decimated(args):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
+    # eq. (17)'s comparison: the plain length-N transform (alpha = 1) of the
+    # same signals, whose every p-th bin is the alpha = 1/p spectrum
+    if args.tune:
+        dd.dense_dft_tune(N, 1, batch, dd.DD_C64)
+    plan_full = dd.dense_dft_plan(N, 1, T, batch, dd.DD_C64)
+    Xf = torch.empty(batch, N, dtype=torch.complex64, device="cuda")
+    for _ in range(args.warmup):
+        dd.dense_dft_exec(plan_full, xd, Xf, stream=sp)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        dd.dense_dft_exec(plan_full, xd, Xf, stream=sp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_full = e0.elapsed_time(e1) / args.steps
+    dec = Xf[:, ::p]
+    full_vs_dec = float((dec - X).abs().pow(2).sum().sqrt() / dec.abs().pow(2).sum().sqrt())
     b_alg = batch * (N * 8 + (N // p) * 8)
     res = {
-        "metric": "dense-spectrum bins/s & % HBM peak, batched vs plain at rel L2<=1e-5; p50/p99",
+        "metric": METRIC,
         "value": batch * (N // p) / (ms * 1e-3), "unit": "bins/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "decimated", "batch": batch, "N": N, "alpha": f"1/{p}", "input": "complex64",
                    "schedule_of_length_N_over_p": dd.dense_dft_plan_get_sched(plan)},
+        "eq17": {"alpha_1_over_p_ms": ms, "plain_length_N_ms": ms_full, "speedup": ms_full / ms,
+                 "plain_length_N_schedule": dd.dense_dft_plan_get_sched(plan_full),
+                 "rel_l2_plain_decimated_vs_alpha_1_over_p": full_vs_dec,
+                 "what": "alpha = 1/p (fold + length-N/p transform) against the length-N transform "
+                         "whose every p-th bin is the same spectrum, same signals and GPU"},
         "roofline": {"bound": "hbm", "achieved": b_alg / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "what": "end to end per step (fold + transform): algorithmic bytes batch*(N*8 + N/p*8)"},
@@ -551,7 +661,7 @@ def run_decimated(args):
         res["rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         res["cpu_baseline"] = {"value": len(ref) / el, "unit": "bins/s", "cores": oracle.threads(), "kind": "oracle",
                                "sample": f"all {len(ref)} bins of signal 0 ({N} complex multiply-adds each), {el:.1f} s"}
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def main():
@@ -559,7 +669,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="batch_c64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="headline", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="use the planner's built-in schedule rules instead of tuning first")
@@ -570,6 +680,9 @@ def main():
                     help="default, real-input, inverse and uneven workloads: load the tuning table "
                          "from PATH if it exists, else tune and save it there (profiling runs then "
                          "time the same schedules)")
+    ap.add_argument("--sched", default="", metavar="N1xN2[:JGROUP[:CHUNK]]",
+                    help="plain workloads: run this two-pass schedule instead of tuning (profiles name "
+                         "their schedule this way, so that a re-take times the same launches)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="instead of the transform, run --steps plain device copies of MIB MiB "
                          "(calibrates the profiler's HBM byte counters)")
@@ -596,44 +709,73 @@ def main():
                           "GBps_read_plus_write": 2 * n * args.steps / el / 1e9}))
         return
 
+    import paper_2403_16665_amd as dd  # noqa: F401  (fails loudly without the built library)
+
+    runners = {"headline": run_headline, "uneven": run_uneven, "serving": run_serving,
+               "ablation": run_ablation, "inverse": run_inverse, "decimated": run_decimated}
+    fn = runners.get(args.workload)
+    result = fn(args) if fn else run_plain(args, args.workload)
+    print(json.dumps(result), flush=True)
+
+
+def run_headline(args):
+    """The metric's own workloads in one line: the 1000-signal uneven batch
+    (batched vs 1000 plain executions; its bins/s is the line's value), and
+    as sub-records the plain kernel on 256 x 65536 signals at alpha 8 and the
+    request server against plain per-request execution at 1k, 10k and 50k
+    requests/s (p50/p99).  Every class of the mix is tuned once, first."""
     import paper_2403_16665_amd as dd
+    import siggen
+    t0 = time.perf_counter()
+    tuned = False
+    if args.tune and not args.tune_db:
+        # the uneven batch's classes and the serving stream's (the same sampler)
+        mix = siggen.uneven_mix(siggen.rngs(3, 1)[0], 1000) + siggen.uneven_mix(siggen.rngs(5, 1)[0], 10000)
+        tuning = tune_classes(dd, mix, dtypes=(dd.DD_C64, dd.DD_F32))
+        tuned = True
+    result = run_uneven(args, tuned=tuned)
+    if tuned:
+        result["tuning"] = tuning
+    sub = argparse.Namespace(**vars(args))
+    sub.no_cpu = True
+    result["plain_kernel_256x65536_a8"] = run_plain(sub, "batch_c64", oracle_signals=4)
+    result["serving"] = run_serving(sub, rates=[1000.0, 10000.0, 50000.0], counts=[4000, 10000, 10000],
+                                    tuned=tuned)
+    result["seconds_total"] = time.perf_counter() - t0
+    return result
 
-    if args.workload == "uneven":
-        run_uneven(args)
-        return
-    if args.workload == "serving":
-        run_serving(args)
-        return
-    if args.workload == "ablation":
-        run_ablation(args)
-        return
-    if args.workload == "inverse":
-        run_inverse(args)
-        return
-    if args.workload == "decimated":
-        run_decimated(args)
-        return
 
-    w = WORKLOADS[args.workload]
+def run_plain(args, name, oracle_signals=0):
+    """One plain transform (one dense_dft_exec over the whole batch) of a
+    fixed-shape workload, timed; returns the record.  oracle_signals > 0:
+    without the CPU-baseline leg, the first that many signals are still
+    checked against the oracle on 1024 seeded bins each."""
+    import torch
+    import paper_2403_16665_amd as dd
+    w = WORKLOADS[name]
     N, alpha, batch, dt = w["N"], w["alpha"], w["batch"], w["dt"]
     T = N * dt
     M = alpha * N
-    x = make_inputs(args.workload, w)
+    x = make_inputs(name, w)
     dev = torch.device("cuda:0")
     xd = torch.from_numpy(x).to(dev)
     code = dd.dtype_code(xd.dtype)
     tuning = None
-    if args.tune_db and os.path.exists(args.tune_db):
-        # a table saved by an earlier run: the same schedules, no tuner launches
-        dd.dense_dft_tune_load(args.tune_db)
-        tuning = {"loaded": args.tune_db}
-    elif args.tune:
-        t_tune = time.perf_counter()
-        tuning = dd.dense_dft_tune(N, alpha, batch, code)
-        tuning["seconds"] = time.perf_counter() - t_tune
-        if args.tune_db:
-            dd.dense_dft_tune_save(args.tune_db)
-    plan = dd.dense_dft_plan(N, alpha, T, batch, code)
+    if args.sched:
+        plan = dd.dense_dft_plan_sched(N, alpha, T, batch, code, parse_sched(args.sched))
+        tuning = {"schedule_given": args.sched}
+    else:
+        if args.tune_db and os.path.exists(args.tune_db):
+            # a table saved by an earlier run: the same schedules, no tuner launches
+            dd.dense_dft_tune_load(args.tune_db)
+            tuning = {"loaded": args.tune_db}
+        elif args.tune:
+            t_tune = time.perf_counter()
+            tuning = dd.dense_dft_tune(N, alpha, batch, code)
+            tuning["seconds"] = time.perf_counter() - t_tune
+            if args.tune_db:
+                dd.dense_dft_tune_save(args.tune_db)
+        plan = dd.dense_dft_plan(N, alpha, T, batch, code)
     Xd = torch.empty((batch, M), dtype=dd.out_dtype(code), device=dev)
     stream = torch.cuda.Stream(device=dev)
     sp = stream.cuda_stream
@@ -696,7 +838,7 @@ def main():
     value = bins_per_step / (ms_per_step * 1e-3)
     achieved = b_alg / (kernel_ms_per_step * 1e-3) / 1e9
     result = {
-        "metric": "dense-spectrum bins/s & % HBM peak, batched vs plain at rel L2<=1e-5; p50/p99",
+        "metric": METRIC,
         "value": value,
         "unit": "bins/s",
         "n_gpus": 1,
@@ -709,7 +851,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if out_bytes == 16 else "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "batch": batch, "N": N, "alpha": alpha,
+        "config": {"workload": name, "batch": batch, "N": N, "alpha": alpha,
                    "dt": dt, "T": T, "input": w["input"], "bins_per_signal": M,
                    "schedule": dd.dense_dft_plan_get_sched(plan)},
         "tuning": tuning,
@@ -718,16 +860,16 @@ def main():
         "copy_ceiling_GBps": copy_gbs,
         "kernels": kernels,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name),
                      "what": "whole transform per step (all its kernels): algorithmic bytes "
                              "batch*(N*s_in + alpha*N*s_out) / summed kernel durations"},
     }
     traffic = result["roofline"]["traffic"]
     if traffic:
         result["roofline"]["amplification"] = traffic / b_alg   # measured HBM bytes / algorithmic
-    if args.workload == "precision":
+    if name == "precision":
         result["precision"] = precision_errors(dd, xd, Xd, N, alpha, T)
-    if args.workload == "real_f32":
+    if name == "real_f32":
         # the same samples through the complex path, which transforms every
         # scratch row instead of the Hermitian half
         xc = xd.to(torch.complex64)
@@ -758,7 +900,20 @@ def main():
         result["rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         result["rel_l2_bins"] = int(len(ref))
         result["cpu_baseline"] = cpu
-    print(json.dumps(result), flush=True)
+    elif oracle_signals:
+        import oracle
+        import siggen
+        rng = np.random.default_rng(456)
+        got, ref = [], []
+        for b in range(min(oracle_signals, batch)):
+            bins = siggen.bin_subset(rng, M, 1024)
+            ref.append(oracle.alpha_dft_bins(x[b], alpha, T, bins))
+            got.append(Xd[b].cpu().numpy()[bins])
+        got, ref = np.concatenate(got), np.concatenate(ref)
+        result["rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        result["rel_l2_bins"] = int(len(ref))
+    del Xd, xd
+    return result
 
 
 if __name__ == "__main__":

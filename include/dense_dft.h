@@ -70,9 +70,13 @@ typedef enum dd_status {
 
 /* Plan flags.  Twiddle factors are always indexed by an exponent reduced
  * exactly in integers (q = j*n, k*n ... mod the transform length).
- *   DD_TWIDDLE_FP64: each factor is generated on the GPU in double precision
- *                    (sin/cos of 2 pi q / L) and rounded once to the working
- *                    precision (the default).
+ *   DD_TWIDDLE_FP64: each table entry is generated on the GPU in double
+ *                    precision (sin/cos of 2 pi q / L) and rounded once to
+ *                    the working precision (the default).  The inter-pass
+ *                    factor of a two-pass schedule, W_{alpha N}^{m1 n2}, is
+ *                    the working-precision product of two such entries
+ *                    (W_N^{k1 n2} W_{alpha N}^{j n2}), so it carries up to
+ *                    three roundings; every other factor is one entry.
  *   DD_TWIDDLE_FP32: the angle and sin/cos are evaluated in single precision
  *                    from the same exact integer q (the low-precision variant
  *                    the precision study compares against).  Ignored for
@@ -365,10 +369,15 @@ dd_status dense_dft_exec_many(const dd_desc *descs, int32_t count,
  * A server keeps on one device: a scratch pool of hbm_budget_bytes, the
  * twiddle tables of every (N, alpha) class it has met (and plain plans for
  * requests outside the batch kernel), and max_inflight execution slots, each
- * with a stream, an event and a HIP graph of the persistent batch launch
- * captured once at creation (its descriptor table is re-read from pinned
- * host memory at every replay, so one graph serves batches of any mix).
- * A scheduler thread fills a slot whenever one is free.  Requests above
+ * with a stream, an event and HIP graphs of the persistent batch launch
+ * captured once at creation, one per grid size (16, 64, 256 blocks and the
+ * device's occupancy; a batch replays the smallest that covers its tasks;
+ * the descriptor table is re-read from pinned host memory at every replay,
+ * so one graph serves batches of any mix).
+ * A scheduler thread fills a slot whenever one is free.  While at most two
+ * requests are queued and each can have a free slot, the head takes a slot
+ * alone (at light load requests run concurrently on separate slots, which
+ * beats a batch launch of so few); beyond that, batches form.  Requests above
  * batch_max_bins and the ones the batch kernel is not built for run as
  * plain executions of resident plans (with the schedules the tuner
  * recorded), each in a slot of its own when it reaches the head of the
@@ -391,9 +400,10 @@ typedef struct dd_server *dd_server_t;
 #define DD_SERVE_BATCHED 0
 #define DD_SERVE_PLAIN 1
 /* Server flag: every request the batch kernel can run goes through it, even
- * alone, so that a result does not depend on what else was queued (bit for
- * bit).  Without it a batch of one runs as a plain execution (lower latency
- * when the server is idle; the same result within the FP32 tolerance). */
+ * alone, and whatever is queued forms a batch, so that a result does not
+ * depend on what else was queued (bit for bit).  Without it a batch of one
+ * runs as a plain execution (lower latency when the server is idle; the same
+ * result within the FP32 tolerance). */
 #define DD_SERVE_DETERMINISTIC 0x100u
 
 typedef struct dd_server_cfg {
@@ -401,7 +411,7 @@ typedef struct dd_server_cfg {
     int32_t mode;             /* DD_SERVE_BATCHED, or DD_SERVE_PLAIN: every request runs
                                  alone as a plain execution (the per-request baseline) */
     size_t hbm_budget_bytes;  /* footprint bound and scratch pool size; 0 -> 8 GiB */
-    int32_t max_inflight;     /* slots; 0 -> 6 (batched) or 8 (plain); at most 64 */
+    int32_t max_inflight;     /* slots; 0 -> 8; at most 64 */
     int32_t max_batch;        /* requests per batch; 0 -> 256; at most 4096 (plain: 1) */
     int32_t max_queue;        /* queued, not yet admitted requests; 0 -> 65536 */
     uint32_t flags;           /* DD_TWIDDLE_FP64 or DD_TWIDDLE_FP32, | DD_SERVE_DETERMINISTIC */

@@ -12,7 +12,13 @@
 //   * it stops at the first kernel request that `reserve` refuses (the
 //     memory budget or the scratch pool), so kernel requests keep their
 //     order;
-//   * in plain mode every request takes a slot alone.
+//   * in plain mode every request takes a slot alone;
+//   * in batched mode, while no more than `solo_upto` requests are queued,
+//     the head takes the slot alone too: a lightly loaded server runs each
+//     request as soon as a slot frees, concurrently on separate slots, which
+//     is faster than one batch launch of so few (a batch launch pays its
+//     staging and queue kernels; it wins once requests outnumber the slots
+//     that could run them).
 #pragma once
 
 #include <vector>
@@ -25,9 +31,9 @@ namespace dd {
 // claimed) when r does not fit now.
 template <class Queue, class IsKernel, class Reserve>
 void admit_requests(Queue& pending, int cap, bool plain_mode, IsKernel is_kernel, Reserve reserve,
-                    std::vector<typename Queue::value_type>& take) {
+                    std::vector<typename Queue::value_type>& take, int solo_upto = 0) {
   if (pending.empty() || cap < 1) return;
-  if (plain_mode || !is_kernel(pending.front())) {
+  if (plain_mode || !is_kernel(pending.front()) || (int)pending.size() <= solo_upto) {
     if (reserve(pending.front())) {
       take.push_back(pending.front());
       pending.pop_front();

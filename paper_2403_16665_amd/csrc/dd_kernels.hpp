@@ -543,7 +543,7 @@ __global__ __launch_bounds__(ROWS * (L / make_line_plan(L).EPT)) void k_pass2(co
 
 // ---------------------------------------------------------------------------
 // Twiddle tables: out[r][c] = W_den^{((r + r0) c) mod den}, exponent reduced
-// exactly in 64-bit integers, then sin/cos in FP64 (rounded once to R) or,
+// exactly in 64-bit integers, then sin/cos in FP64 (each entry rounded once to R) or,
 // for the FP32 variant, angle and sin/cos in FP32 from the same exact q.
 // ---------------------------------------------------------------------------
 template <typename R>

@@ -57,14 +57,27 @@ struct Req {
   dd_result res{};
 };
 
+// Grid variants of a slot's captured batch launch: variant v runs at most
+// 16 * 4^v blocks per queue kernel (the last: the device's occupancy), and a
+// batch replays the smallest variant whose grids cover its task counts, so a
+// batch of a few requests does not pay a device-wide launch.
+constexpr int GRID_VARIANTS = 4;
+inline int variant_grid(int v, int full) {
+  return v == GRID_VARIANTS - 1 ? full : std::min(full, 16 << (2 * v));
+}
+
+// Queued requests at or below which the head takes a slot alone, when there
+// are as many free slots (the admission policy's light-load rule).
+constexpr int SOLO_UPTO = 2;
+
 struct Slot {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipEvent_t done = nullptr;
-  // graphs of the batch launch: [0] one queue launch (no two-pass item),
-  // [1] both; their staging kernel reads `tab` at every replay
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  // graphs of the batch launch per grid variant: [0] one queue launch (no
+  // two-pass item), [1] both; their staging kernel reads `tab` at every replay
+  hipGraph_t graph[2][GRID_VARIANTS] = {};
+  hipGraphExec_t exec[2][GRID_VARIANTS] = {};
   BatchTable tab;
   std::vector<Req*> reqs;
   bool busy = false;
@@ -158,7 +171,15 @@ bool launch_slot(dd_server* s, Slot& slot, std::unique_lock<std::mutex>& lk) {
     s->stats.peak_footprint = std::max(s->stats.peak_footprint, s->used);
     return true;
   };
-  admit_requests(s->pending, cap, plain_mode(s), [](const Req* r) { return r->kernel; }, reserve, take);
+  // light load: as long as every queued request can have a free slot of its
+  // own (at most SOLO_UPTO of them), the head goes alone; deterministic mode
+  // batches whatever is queued (results must not depend on the mix, so a
+  // request never takes the plain path instead)
+  int free_slots = 0;
+  for (const Slot& o : s->slots) free_slots += o.busy ? 0 : 1;
+  const int solo_upto = (s->cfg.flags & DD_SERVE_DETERMINISTIC) ? 0 : std::min(SOLO_UPTO, free_slots);
+  admit_requests(s->pending, cap, plain_mode(s), [](const Req* r) { return r->kernel; }, reserve, take,
+                 solo_upto);
   if (take.empty()) return false;
   slot.busy = true;
   lk.unlock();
@@ -190,8 +211,15 @@ bool launch_slot(dd_server* s, Slot& slot, std::unique_lock<std::mutex>& lk) {
     if (st == DD_OK && !kreq.empty()) assign_task_offsets(slot.tab.items(), (int)kreq.size(), slot.tab.host);
     const uint64_t t0 = clock_ns();
     for (Req* r : take) r->res.t_start_ns = t0;
-    if (st == DD_OK && !kreq.empty())
-      st = hip_status(hipGraphLaunch(slot.exec[slot.tab.host->n_second > 0 ? 1 : 0], slot.stream));
+    if (st == DD_OK && !kreq.empty()) {
+      const BatchMeta& m = *slot.tab.host;
+      int v = 0;
+      while (v < GRID_VARIANTS - 1 &&
+             (variant_grid(v, s->grid1) < std::min(m.n_first, s->grid1) ||
+              variant_grid(v, s->grid2) < std::min(m.n_second, s->grid2)))
+        ++v;
+      st = hip_status(hipGraphLaunch(slot.exec[m.n_second > 0 ? 1 : 0][v], slot.stream));
+    }
     for (size_t i = 0; i < freq.size() && st == DD_OK; ++i) {
       Req* r = freq[i];
       dd_plan_t p = nullptr;
@@ -271,10 +299,11 @@ void worker_main(dd_server* s) {
 }
 
 void free_slot(Slot& sl) {
-  for (int g = 0; g < 2; ++g) {
-    if (sl.exec[g]) (void)hipGraphExecDestroy(sl.exec[g]);
-    if (sl.graph[g]) (void)hipGraphDestroy(sl.graph[g]);
-  }
+  for (int g = 0; g < 2; ++g)
+    for (int v = 0; v < GRID_VARIANTS; ++v) {
+      if (sl.exec[g][v]) (void)hipGraphExecDestroy(sl.exec[g][v]);
+      if (sl.graph[g][v]) (void)hipGraphDestroy(sl.graph[g][v]);
+    }
   if (sl.done) (void)hipEventDestroy(sl.done);
   if (sl.own_stream && sl.stream) (void)hipStreamDestroy(sl.stream);
   free_table(sl.tab);
@@ -296,9 +325,10 @@ void free_server(dd_server* s) {
   s->reqs.clear();
 }
 
-// One slot: buffers, event, stream, and the graph of a batch launch over
-// its descriptor table (grid fixed to the device's occupancy at the batch
-// kernel's largest LDS, so that one graph fits any composition).
+// One slot: buffers, event, stream, and the graphs of a batch launch over
+// its descriptor table (one per grid variant, the largest at the device's
+// occupancy at the batch kernel's largest LDS, so that every composition
+// has a graph that fits it).
 dd_status make_slot(dd_server* s, Slot& sl) {
   const int cap = s->cfg.max_batch;
   dd_status st = DD_OK;
@@ -317,16 +347,16 @@ dd_status make_slot(dd_server* s, Slot& sl) {
   st = hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   if (st != DD_OK) return st;
   hipError_t e = hipSuccess;
-  for (int g = 0; g < 2 && e == hipSuccess; ++g) {
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) break;
-    const hipError_t e1 =
-        launch_batch(sl.tab.host_dev, sl.tab.dev, cap, sl.tab.ctl, s->grid1, g ? s->grid2 : 0, BATCH_LDS_MAX,
-                     batch_lds2_max(), cs);
-    e = hipStreamEndCapture(cs, &sl.graph[g]);
-    if (e == hipSuccess) e = e1;
-    if (e == hipSuccess) e = hipGraphInstantiate(&sl.exec[g], sl.graph[g], nullptr, nullptr, 0);
-  }
+  for (int g = 0; g < 2 && e == hipSuccess; ++g)
+    for (int v = 0; v < GRID_VARIANTS && e == hipSuccess; ++v) {
+      e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) break;
+      const hipError_t e1 = launch_batch(sl.tab.host_dev, sl.tab.dev, cap, sl.tab.ctl, variant_grid(v, s->grid1),
+                                         g ? variant_grid(v, s->grid2) : 0, BATCH_LDS_MAX, batch_lds2_max(), cs);
+      e = hipStreamEndCapture(cs, &sl.graph[g][v]);
+      if (e == hipSuccess) e = e1;
+      if (e == hipSuccess) e = hipGraphInstantiate(&sl.exec[g][v], sl.graph[g][v], nullptr, nullptr, 0);
+    }
   (void)hipStreamDestroy(cs);
   return hip_status(e);
 }
@@ -367,7 +397,7 @@ dd_status dense_dft_server_create(const dd_server_cfg* cfg, dd_server_t* out) {
   if (c.flags & ~(uint32_t)(DD_TWIDDLE_FP32 | DD_SERVE_DETERMINISTIC)) return DD_ERR_INVALID;
   if (c.batch_max_bins < -1) return DD_ERR_INVALID;
   if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = (size_t)8 << 30;
-  if (c.max_inflight == 0) c.max_inflight = c.mode == DD_SERVE_PLAIN ? 8 : 6;
+  if (c.max_inflight == 0) c.max_inflight = 8;
   if (c.max_batch == 0) c.max_batch = 256;
   if (c.mode == DD_SERVE_PLAIN) c.max_batch = 1;
   if (c.max_queue == 0) c.max_queue = 65536;

@@ -36,7 +36,7 @@ struct Server {
   size_t budget, used = 0;
   dd::RangeAlloc pool;
   Server(size_t b, size_t pool_bytes) : budget(b) { pool.reset(pool_bytes); }
-  std::vector<R*> round(std::deque<R*>& q, int cap, bool plain) {
+  std::vector<R*> round(std::deque<R*>& q, int cap, bool plain, int solo_upto = 0) {
     std::vector<R*> take;
     auto reserve = [&](R* r) {
       if (used + r->footprint > budget) return false;
@@ -45,7 +45,7 @@ struct Server {
       used += r->footprint;
       return true;
     };
-    dd::admit_requests(q, cap, plain, [](const R* r) { return r->kernel; }, reserve, take);
+    dd::admit_requests(q, cap, plain, [](const R* r) { return r->kernel; }, reserve, take, solo_upto);
     return take;
   }
 };
@@ -126,6 +126,20 @@ int main() {
     Server s(1000, 0);
     auto t = s.round(q, 8, true);
     expect(ids(t) == "1 " && q.size() == 2, "plain mode: got " + ids(t));
+  }
+  {  // light load: up to solo_upto queued requests go one per slot, more form a batch
+    auto q = queue({1, 2});
+    Server s(1000, 0);
+    auto t = s.round(q, 8, false, 2);
+    expect(ids(t) == "1 " && q.size() == 1, "solo at light load: got " + ids(t));
+    t = s.round(q, 8, false, 2);
+    expect(ids(t) == "2 " && q.empty(), "the second solo too: got " + ids(t));
+    auto q3 = queue({3, 4, 5});
+    t = s.round(q3, 8, false, 2);
+    expect(ids(t) == "3 4 5 " && q3.empty(), "three queued form a batch: got " + ids(t));
+    auto q1 = queue({6});
+    t = s.round(q1, 8, false, 0);
+    expect(ids(t) == "6 ", "solo_upto 0 keeps the batch path: got " + ids(t));
   }
   {  // nothing queued
     std::deque<R*> q;

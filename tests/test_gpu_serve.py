@@ -247,3 +247,33 @@ def test_serve_caller_stream_and_fp32_twiddles(oracle_mod):
                      f"fp32-twiddle server N={N} alpha={a}", full_rms=spectrum_rms(x, N * 1e-3))
         ref = dd.alpha_dft(xs[i], a, N * 1e-3, flags=dd.DD_TWIDDLE_FP32).cpu().numpy()
         assert_same(got, ref, f"fp32-twiddle served vs plain, request {i}")
+
+
+def test_class_schedule_survives_a_tuning_change(oracle_mod, tmp_path):
+    """A class's schedule is fixed when the server first makes its tables: a
+    later change of the tuning table (here: the two-pass entry the class was
+    first served with is cleared, so the class now classifies as one pass)
+    must not change what the server's kernel items use (their scratch
+    included).  Both requests are checked against the oracle."""
+    import paper_2403_16665_amd as dd
+    N, alpha = 1024, 4
+    db = tmp_path / "two_pass.txt"
+    db.write_text(f"batch {N} {alpha} 2 32 32 1.0\n")
+    dd.dense_dft_tune_clear()
+    dd.dense_dft_tune_load(str(db))
+    try:
+        srv = dd.dense_dft_server_create(hbm_budget_bytes=1 << 28, max_inflight=1, max_batch=4,
+                                         flags=dd.DD_SERVE_DETERMINISTIC, batch_max_bins=-1)
+        reqs = make_requests(77, 0, extra=[(N, alpha), (N, alpha)])
+        xs, Xs = device_buffers(reqs)
+        serve_all(srv, reqs[:1], xs[:1], Xs[:1])        # class tables made with the two-pass entry
+        dd.dense_dft_tune_clear()                       # the class now classifies as one pass
+        serve_all(srv, reqs[1:], xs[1:], Xs[1:])
+        st = dd.dense_dft_server_stats(srv)
+        assert st["kernel_requests"] == 2 and st["classes"] == 1
+        dd.dense_dft_server_destroy(srv)
+    finally:
+        dd.dense_dft_tune_clear()
+    for (n, a, c, x), X in zip(reqs, Xs):
+        ref = oracle_mod.alpha_dft(x, a, n * 1e-3)
+        assert_close(X.cpu().numpy(), ref, "f32", f"N={n} alpha={a}")
