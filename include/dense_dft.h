@@ -154,6 +154,29 @@ dd_status dense_dft_workspace_size(dd_plan_t plan, size_t *bytes);
 dd_status dense_dft_exec(dd_plan_t plan, const void *x, void *X,
                          void *workspace, void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * forward transform of dense_dft_exec, with the two-pass scratch taken from
+ * a fixed device array of DD_STATIC_SCRATCH_BYTES that the library holds on
+ * each device it runs on until the process ends, instead of a workspace.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); the first call on a device looks the array's address up once.
+ * A batch runs in chunks of as many signals as the array holds (each
+ * signal's arithmetic is that of dense_dft_exec: the results are identical).
+ * Nothing in the array needs to start at zero (pass 1 writes every element
+ * pass 2 reads); it keeps the last call's contents.
+ * Every call on a device shares that device's array: calls whose executions
+ * overlap in time on one device (other streams, other host threads) race
+ * and corrupt each other's results; order them on one stream.  The plan
+ * itself (made beforehand) owns its twiddle tables; create it with
+ * DD_NO_WORKSPACE to allocate no workspace at all.
+ *   plan, x, X, stream : as dense_dft_exec.
+ * Errors: as dense_dft_exec; DD_ERR_TOO_LARGE when one signal's scratch
+ *         (alpha*N output elements) exceeds DD_STATIC_SCRATCH_BYTES;
+ *         DD_ERR_UNSUPPORTED for alpha = 1/p plans (dense_dft_plan_decimated). */
+#define DD_STATIC_SCRATCH_BYTES (64u << 20)
+dd_status dense_dft_exec_static(dd_plan_t plan, const void *x, void *X, void *stream);
+
 /* Enqueue the inverse transform of all `batch` spectra of the plan on
  * `stream` (the reading of eq. (7), second line, with the factor 1/(alpha T)
  * that undoes the forward transform of eq. (2)):

@@ -43,6 +43,8 @@ _lib.dense_dft_exec.restype = ctypes.c_int
 _lib.dense_dft_plan_decimated.argtypes = [ctypes.POINTER(_vp), _i64, ctypes.c_int32, ctypes.c_double, _i64,
                                           ctypes.c_int, ctypes.c_uint32]
 _lib.dense_dft_plan_decimated.restype = ctypes.c_int
+_lib.dense_dft_exec_static.argtypes = [_vp, _vp, _vp, _vp]
+_lib.dense_dft_exec_static.restype = ctypes.c_int
 _lib.dense_dft_exec_inverse.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.dense_dft_exec_inverse.restype = ctypes.c_int
 _lib.dense_dft_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -271,6 +273,22 @@ def dense_dft_exec(plan: Plan, x, X, workspace=None, stream=None) -> None:
         stream = torch.cuda.current_stream(x.device).cuda_stream
     _check(_lib.dense_dft_exec(plan.handle, _ptr(x), _ptr(X), _ptr(workspace), _vp(stream)),
            "dense_dft_exec")
+
+
+DD_STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def dense_dft_exec_static(plan: Plan, x, X, stream=None) -> None:
+    """The forward transform without any allocation: the two-pass scratch is
+    the library's fixed per-device array of DD_STATIC_SCRATCH_BYTES (calls on
+    one device share it, so their executions must not overlap in time).
+    x, X, stream: as dense_dft_exec."""
+    _check_buf(x, "x", in_dtype(plan.dtype), plan.batch * plan.N)
+    _check_buf(X, "X", out_dtype(plan.dtype), plan.batch * plan.M)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+    _check(_lib.dense_dft_exec_static(plan.handle, _ptr(x), _ptr(X), _vp(stream)), "dense_dft_exec_static")
 
 
 KERNEL_KINDS = {1: "single", 2: "pass1", 3: "pass2", 4: "inverse_single", 5: "inverse_passA", 6: "inverse_passB"}

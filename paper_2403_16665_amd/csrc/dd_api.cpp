@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -518,8 +519,11 @@ dd_status dense_dft_plan_info(dd_plan_t p, int32_t* passes, int64_t* N1, int64_t
 
 namespace {
 
+// chunk: signals per pass pair of a two-pass plan (the plan's own, or fewer
+// when the scratch is smaller than the plan's workspace); each signal's
+// arithmetic does not depend on it.
 template <typename R, typename In>
-dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s) {
+dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s, int64_t chunk) {
   const R scale = (R)(p->T / (double)p->N);
   const int64_t M = (int64_t)p->alpha * p->N;
   if (p->passes == 1) {
@@ -545,8 +549,8 @@ dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s
     }
     return DD_OK;
   }
-  for (int64_t c0 = 0; c0 < p->batch; c0 += p->chunk) {
-    const int64_t nb = p->batch - c0 < p->chunk ? p->batch - c0 : p->chunk;
+  for (int64_t c0 = 0; c0 < p->batch; c0 += chunk) {
+    const int64_t nb = p->batch - c0 < chunk ? p->batch - c0 : chunk;
     DenseArgs<R> a1{};
     a1.batch = nb;
     a1.x_stride = p->N;
@@ -653,9 +657,87 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   return x < y + nb && y < x + na;
 }
 
+// The forward transform of a validated plain plan, by input dtype.
+dd_status exec_dispatch(dd_plan* p, const void* x, void* X, void* ws, hipStream_t s, int64_t chunk) {
+  switch (p->dtype) {
+    case DD_F32:
+      return exec_typed<float>(p, static_cast<const float*>(x), static_cast<cx<float>*>(X),
+                               static_cast<cx<float>*>(ws), s, chunk);
+    case DD_C64:
+      return exec_typed<float>(p, static_cast<const cx<float>*>(x), static_cast<cx<float>*>(X),
+                               static_cast<cx<float>*>(ws), s, chunk);
+    case DD_F64:
+      return exec_typed<double>(p, static_cast<const double*>(x), static_cast<cx<double>*>(X),
+                                static_cast<cx<double>*>(ws), s, chunk);
+    case DD_C128:
+      return exec_typed<double>(p, static_cast<const cx<double>*>(x), static_cast<cx<double>*>(X),
+                                static_cast<cx<double>*>(ws), s, chunk);
+  }
+  return DD_ERR_INVALID;
+}
+
+// Scratch of dense_dft_exec_static: a fixed device array that each device
+// the library runs on holds until the process ends.  Host code never uses
+// the array's name as an address (on the host it is a stand-in, not device
+// memory): its device address is looked up once per device and kept.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)DD_STATIC_SCRATCH_BYTES;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[STATIC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on `dev` (made current for the lookup).
+dd_status static_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= STATIC_MAX_DEVICES) return DD_ERR_DEVICE;
+  std::lock_guard<std::mutex> g(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return DD_ERR_DEVICE;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return DD_ERR_DEVICE;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return DD_ERR_DEVICE;
+    }
+    g_static_ptr[dev] = ptr;
+  }
+  *out = g_static_ptr[dev];
+  return DD_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+dd_status dense_dft_exec_static(dd_plan_t p, const void* x, void* X, void* stream) {
+  if (!p || !x || !X) return DD_ERR_INVALID;
+  if (p->inner) return DD_ERR_UNSUPPORTED;
+  const size_t out_cx = cx_bytes(p);
+  if ((uintptr_t)x % p->in_bytes != 0 || (uintptr_t)X % out_cx != 0) return DD_ERR_INVALID;
+  const size_t in_total = (size_t)p->batch * p->N * p->in_bytes;
+  const size_t out_total = (size_t)p->batch * p->alpha * p->N * out_cx;
+  if (overlaps(x, in_total, X, out_total)) return DD_ERR_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->passes == 1) return exec_dispatch(p, x, X, nullptr, s, p->chunk);
+  // two passes: as many signals per pass pair as the array holds, at most
+  // the plan's own chunk (within one dispatch's grid)
+  const size_t per_sig = (size_t)p->alpha * p->N * out_cx;
+  if (per_sig > STATIC_SCRATCH_BYTES) return DD_ERR_TOO_LARGE;
+  int64_t chunk = (int64_t)(STATIC_SCRATCH_BYTES / per_sig);
+  if (chunk > p->chunk) chunk = p->chunk;
+  void* ws = nullptr;
+  const dd_status st = static_scratch(p->device, &ws);
+  if (st != DD_OK) return st;
+  return exec_dispatch(p, x, X, ws, s, chunk);
+}
 
 dd_status dense_dft_exec(dd_plan_t p, const void* x, void* X, void* workspace, void* stream) {
   if (!p || !x || !X) return DD_ERR_INVALID;
@@ -686,22 +768,7 @@ dd_status dense_dft_exec(dd_plan_t p, const void* x, void* X, void* workspace, v
     if (overlaps(ws, p->ws_bytes, X, out_total) || overlaps(ws, p->ws_bytes, x, in_total))
       return DD_ERR_INVALID;
   }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  switch (p->dtype) {
-    case DD_F32:
-      return exec_typed<float>(p, static_cast<const float*>(x), static_cast<cx<float>*>(X),
-                               static_cast<cx<float>*>(ws), s);
-    case DD_C64:
-      return exec_typed<float>(p, static_cast<const cx<float>*>(x), static_cast<cx<float>*>(X),
-                               static_cast<cx<float>*>(ws), s);
-    case DD_F64:
-      return exec_typed<double>(p, static_cast<const double*>(x), static_cast<cx<double>*>(X),
-                                static_cast<cx<double>*>(ws), s);
-    case DD_C128:
-      return exec_typed<double>(p, static_cast<const cx<double>*>(x), static_cast<cx<double>*>(X),
-                                static_cast<cx<double>*>(ws), s);
-  }
-  return DD_ERR_INVALID;
+  return exec_dispatch(p, x, X, ws, static_cast<hipStream_t>(stream), p->chunk);
 }
 
 dd_status dense_dft_exec_inverse(dd_plan_t p, const void* X, void* x, void* workspace, void* stream) {

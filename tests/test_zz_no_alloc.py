@@ -1,0 +1,64 @@
+"""The entry point for callers that cannot allocate (dense_dft_exec_static):
+its output against dense_dft_exec's on the same plan, on two calls in a row
+(the second with a smaller input), and against the FP64 oracle; and its
+refusal of a signal whose scratch exceeds the fixed array."""
+import numpy as np
+import pytest
+
+import siggen
+from parity import assert_close, spectrum_rms
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run_pair(oracle_mod, N, alpha, batch, seed):
+    import torch
+    import paper_2403_16665_amd as dd
+    T = N * 1e-3
+    x = np.stack([siggen.tones_complex(g, N, 1e-3) for g in siggen.rngs(seed, batch)])
+    xd = torch.from_numpy(x).cuda()
+    plan = dd.dense_dft_plan(N, alpha, T, batch, dd.DD_C64)
+    Xa = torch.zeros(batch, alpha * N, dtype=torch.complex64, device="cuda")
+    Xb = torch.full_like(Xa, float("nan"))
+    dd.dense_dft_exec(plan, xd, Xa)
+    dd.dense_dft_exec_static(plan, xd, Xb)
+    torch.cuda.synchronize()
+    # each signal's arithmetic is the same whatever the chunking: bit for bit
+    assert torch.equal(Xa, Xb), f"N={N} alpha={alpha}: static-scratch result differs from dense_dft_exec"
+    rng = np.random.default_rng(seed)
+    got = Xb.cpu().numpy()
+    for b in (0, batch - 1):
+        bins = siggen.bin_subset(rng, alpha * N, 512)
+        assert_close(got[b][bins], oracle_mod.alpha_dft_bins(x[b], alpha, T, bins), "f32",
+                     f"static scratch N={N} alpha={alpha} signal {b}", full_rms=spectrum_rms(x[b], T))
+    return plan
+
+
+def test_static_scratch_matches_exec_twice(oracle_mod):
+    import paper_2403_16665_amd as dd
+    # 20 signals x 4 MiB of scratch: the 64 MiB array holds 16, so two chunks
+    p1 = _run_pair(oracle_mod, 65536, 8, 20, 41)
+    assert dd.dense_dft_plan_info(p1)[0] == 2
+    # then a smaller transform through the same array (it keeps the last
+    # call's contents, which the second call must not depend on)
+    p2 = _run_pair(oracle_mod, 16384, 4, 3, 42)
+    assert dd.dense_dft_plan_info(p2)[0] == 2
+
+
+def test_static_scratch_refuses_oversized_signal():
+    import torch
+    import paper_2403_16665_amd as dd
+    N, alpha = 1 << 22, 16          # 512 MiB of scratch per signal
+    plan = dd.dense_dft_plan(N, alpha, 1.0, 1, dd.DD_C64, dd.DD_NO_WORKSPACE)
+    x = torch.zeros(N, dtype=torch.complex64, device="cuda")
+    X = torch.zeros(alpha * N, dtype=torch.complex64, device="cuda")
+    with pytest.raises(dd.DenseDFTError) as e:
+        dd.dense_dft_exec_static(plan, x, X)
+    assert e.value.status == dd.DD_ERR_TOO_LARGE
