@@ -204,7 +204,7 @@ def cpu_baseline(x_rows, alpha, T, M, N, target_s=20.0):
                                f"multiply-adds, FP64 direct sum), {el:.1f} s"}
 
 
-def uneven_oracle_check(xs_np, mix, Xs, dt, nsig=32, nbins=2048, seed=321):
+def uneven_oracle_check(xs_np, mix, Xs, dt, nsig=32, nbins=16384, seed=321):
     """rel L2 of the batched output against the FP64 oracle on seeded bins of
     `nsig` randomly drawn signals of the uneven mix (all bins when a spectrum
     has no more than `nbins`), timed: the oracle's rate on this sample is the

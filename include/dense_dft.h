@@ -397,10 +397,10 @@ dd_status dense_dft_exec_many(const dd_desc *descs, int32_t count,
  * device's occupancy; a batch replays the smallest that covers its tasks;
  * the descriptor table is re-read from pinned host memory at every replay,
  * so one graph serves batches of any mix).
- * A scheduler thread fills a slot whenever one is free.  While at most two
- * requests are queued and each can have a free slot, the head takes a slot
- * alone (at light load requests run concurrently on separate slots, which
- * beats a batch launch of so few); beyond that, batches form.  Requests above
+ * A scheduler thread fills a slot whenever one is free.  While every queued
+ * request can have a free slot of its own, the head takes a slot alone (at
+ * light load requests run concurrently on separate slots, each at its solo
+ * latency); once requests outnumber the free slots, batches form.  Requests above
  * batch_max_bins and the ones the batch kernel is not built for run as
  * plain executions of resident plans (with the schedules the tuner
  * recorded), each in a slot of its own when it reaches the head of the

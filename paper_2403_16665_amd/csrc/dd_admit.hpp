@@ -13,12 +13,12 @@
 //     memory budget or the scratch pool), so kernel requests keep their
 //     order;
 //   * in plain mode every request takes a slot alone;
-//   * in batched mode, while no more than `solo_upto` requests are queued,
-//     the head takes the slot alone too: a lightly loaded server runs each
-//     request as soon as a slot frees, concurrently on separate slots, which
-//     is faster than one batch launch of so few (a batch launch pays its
-//     staging and queue kernels; it wins once requests outnumber the slots
-//     that could run them).
+//   * in batched mode, while no more than `solo_upto` requests are queued
+//     (the server passes its number of free slots), the head takes the slot
+//     alone too: a lightly loaded server runs each request as soon as a slot
+//     frees, concurrently on separate slots, each at its solo latency (a
+//     batch launch pays its staging and queue kernels; it wins once requests
+//     outnumber the slots that could run them).
 #pragma once
 
 #include <vector>

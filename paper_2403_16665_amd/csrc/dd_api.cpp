@@ -45,6 +45,9 @@ struct dd_plan {
   size_t p1_lds = 0;
   int p2_lines = 1, p2_TL = 1, p2_ntile = 1;
   size_t p2_lds = 0;
+  // the forward pass 2 of complex input: wider blocks (up to 1024 threads)
+  int p2f_lines = 1, p2f_ntile = 1;
+  size_t p2f_lds = 0;
   // real input: pass 1 stores the scratch rows m1 <= alpha N1 / 2 and pass 2
   // transforms them in blocks of p2_lines + 1 rows (when those fit the LDS)
   bool p2_half = false;
@@ -211,6 +214,10 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
   p->p2_TL = g2.TL;
   p->p2_ntile = (int)((alpha * N1 + g2.lines - 1) / g2.lines);
   p->p2_lds = lds_pass2((int)N2, g2.lines, p->rbytes);
+  const KGeom g2f = geom_pass2((int)N2, p->rbytes);
+  p->p2f_lines = g2f.lines;
+  p->p2f_ntile = (int)((alpha * N1 + g2f.lines - 1) / g2f.lines);
+  p->p2f_lds = lds_pass2((int)N2, g2f.lines, p->rbytes);
   p->p2h_lds = lds_pass2((int)N2, g2.lines, p->rbytes, g2.lines + 1);
   p->p2_half = (p->dtype == DD_F32 || p->dtype == DD_F64) && p->p2h_lds <= (size_t)LDS_PASS_MAX;
   // signals per pass pair: by default the scratch of one chunk within 128 MiB
@@ -230,27 +237,34 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
   }
   p->p1_jgroup = jg;
   p->p1_njg = (alpha + jg - 1) / jg;
-  // stage the block's pre-twiddles in LDS when they take at most 16 KiB
+  // stage the block's pre-twiddles in LDS when whole rows take at most 16 KiB.
+  // (Their two factors, mode 2, were measured slower for the long columns that
+  // need them here: 2^22 x alpha 16, pass 1 at N1 = 4096 337 -> 512 us.  Its
+  // global loads hold each j's stores back until the previous j's are out,
+  // which keeps its scattered 16-byte stores merging in the L2.)
   const size_t pre_bytes = (size_t)jg * N1 * cx_bytes(p);
+  const size_t cu_lds = 160 * 1024;
   p->p1_pre_lds = pre_bytes <= 16 * 1024 &&
-                  lds_pass1((int)N1, g1.lines, p->rbytes, jg * (int)N1) <= (size_t)LDS_PASS_MAX ? 1 : 0;
-  p->p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, p->p1_pre_lds ? jg * (int)N1 : 0);
+                  lds_pass1((int)N1, g1.lines, p->rbytes, pass1_pre_elems(1, jg, (int)N1)) <= (size_t)LDS_PASS_MAX
+                      ? 1 : 0;
+  p->p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, pass1_pre_elems(p->p1_pre_lds, jg, (int)N1));
   // and the block's W_{alpha N}^{j n2} when they take at most 4 KiB and do
   // not cost a block of residency per CU
   {
-    const int pre_el = p->p1_pre_lds ? jg * (int)N1 : 0;
+    const int pre_el = pass1_pre_elems(p->p1_pre_lds, jg, (int)N1);
     const int q_el = jg * g1.lines;
     const size_t with_q = lds_pass1((int)N1, g1.lines, p->rbytes, pre_el + q_el);
-    const size_t cu = 160 * 1024;
     p->p1_q_lds = (size_t)q_el * cx_bytes(p) <= 4096 && with_q <= (size_t)LDS_PASS_MAX &&
-                  cu / with_q == cu / p->p1_lds ? 1 : 0;
+                  cu_lds / with_q == cu_lds / p->p1_lds ? 1 : 0;
     if (p->p1_q_lds) p->p1_lds = with_q;
   }
   // a chunk's launches must stay within one dispatch's grid: the default
   // chunk shrinks to fit, a requested one that does not fit is refused
   {
     const int64_t b1 = max_launch_blocks(p->p1_lines * p->p1_TL) / ((int64_t)p->p1_ntile * p->p1_njg);
-    const int64_t b2 = max_launch_blocks((p->p2_lines + 1) * p->p2_TL) / p->p2_ntile;
+    int64_t b2 = max_launch_blocks((p->p2_lines + 1) * p->p2_TL) / p->p2_ntile;
+    const int64_t b2f = max_launch_blocks(p->p2f_lines * p->p2_TL) / p->p2f_ntile;
+    if (b2f < b2) b2 = b2f;
     const int64_t cap = b1 < b2 ? b1 : b2;
     if (cap < 1 || (sc.chunk > 0 && chunk > cap)) return DD_ERR_UNSUPPORTED;
     if (chunk > cap) chunk = cap;
@@ -262,7 +276,8 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
   p->inv_p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, p->inv_pre_lds ? alpha * (int)N1 : 0);
   // a column of 4096 doubles with its exchange padding and twiddles exceeds
   // the LDS of a workgroup
-  if (p->p1_lds > (size_t)LDS_PASS_MAX || p->p2_lds > (size_t)LDS_PASS_MAX || p->inv_p1_lds > (size_t)LDS_PASS_MAX)
+  if (p->p1_lds > (size_t)LDS_PASS_MAX || p->p2_lds > (size_t)LDS_PASS_MAX || p->p2f_lds > (size_t)LDS_PASS_MAX ||
+      p->inv_p1_lds > (size_t)LDS_PASS_MAX)
     return DD_ERR_UNSUPPORTED;
   p->ws_bytes = (size_t)chunk * per_sig;
   return DD_OK;
@@ -578,10 +593,11 @@ dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s
     hipError_t e = timed_launch(p, 2, s, [&] { return launch_pass1((int)p->N1, c1, x + c0 * p->N, ws, a1); });
     if (e != hipSuccess) return hip_status(e);
     DenseArgs<R> a2 = a1;
-    a2.lines = p->p2_lines;
-    a2.ntile = half ? (A - H + p->p2_lines - 1) / p->p2_lines : p->p2_ntile;  // blocks of stored rows
+    a2.lines = half ? p->p2_lines : p->p2f_lines;
+    a2.ntile = half ? (A - H + p->p2_lines - 1) / p->p2_lines : p->p2f_ntile;  // blocks of stored rows
     a2.twL = static_cast<const cx<R>*>(p->twL2);
-    LaunchCfg c2{nb * a2.ntile, (p->p2_lines + (half ? 1 : 0)) * p->p2_TL, half ? p->p2h_lds : p->p2_lds, s};
+    LaunchCfg c2{nb * a2.ntile, half ? (p->p2_lines + 1) * p->p2_TL : p->p2f_lines * p->p2_TL,
+                 half ? p->p2h_lds : p->p2f_lds, s};
     e = timed_launch(p, 3, s, [&] {
       return half ? launch_pass2_half((int)p->N2, c2, ws, X + c0 * M, a2)
                   : launch_pass2((int)p->N2, c2, ws, X + c0 * M, a2);

@@ -185,12 +185,16 @@ inline void fill_item(BatchItem& it, const dd_desc& d, const ClassTables& ct, cx
     it.ntile1 = (sc.N2 + C - 1) / C;
     it.jgroup = d.alpha;
     it.njg = 1;
+    // pre-twiddles in LDS: whole rows within 16 KiB, else their two factors
+    // (the j loop then reads no global memory, so it does not wait for the
+    // stores of the previous j)
     it.pre_lds = (size_t)d.alpha * sc.N1 * 8 <= 16 * 1024 ? 1 : 0;
-    // the j loop then reads no global memory, so it does not wait for the
-    // stores of the previous j
+    if (!it.pre_lds &&
+        (size_t)pass1_lds_elems(sc.N1, C, pass1_pre_elems(2, d.alpha, sc.N1)) * 8 <= (size_t)BATCH_LDS_MAX)
+      it.pre_lds = 2;
     it.q_lds = 0;
     const size_t with_q =
-        (size_t)pass1_lds_elems(sc.N1, C, (it.pre_lds ? d.alpha * sc.N1 : 0) + d.alpha * C) * 8;
+        (size_t)pass1_lds_elems(sc.N1, C, pass1_pre_elems(it.pre_lds, d.alpha, sc.N1) + d.alpha * C) * 8;
     if ((size_t)d.alpha * C * 8 <= 4096 && with_q <= (size_t)BATCH_LDS_MAX) it.q_lds = 1;
     it.ntile2 = (d.alpha * sc.N1 + RB - 1) / RB;
     it.p1_tasks = it.ntile1 * it.njg;
@@ -204,7 +208,7 @@ inline void fill_item(BatchItem& it, const dd_desc& d, const ClassTables& ct, cx
 inline size_t item_lds1(const BatchItem& it) {
   if (it.code2 < 0) return batch_single_lds(it.N1, it.alpha, it.lines1);
   const int C = batch_lines(it.N1);
-  return (size_t)pass1_lds_elems(it.N1, C, (it.pre_lds ? it.alpha * it.N1 : 0) + (it.q_lds ? it.alpha * C : 0)) * 8;
+  return (size_t)pass1_lds_elems(it.N1, C, pass1_pre_elems(it.pre_lds, it.alpha, it.N1) + (it.q_lds ? it.alpha * C : 0)) * 8;
 }
 inline size_t item_lds2(const BatchItem& it) { return it.code2 < 0 ? 0 : lds_pass2(it.N2, batch_lines(it.N2), 4); }
 

@@ -36,13 +36,15 @@ hipError_t launch_pass1_impl(int L, const LaunchCfg& c, const In* x, cx<R>* Y, c
   }
 }
 
-// HALF: blocks of RB rows that transform RB + 1 (real input, a.hrows > 0).
+// HALF: blocks of RB rows that transform RB + 1 (real input, a.hrows > 0);
+// otherwise the wider blocks of lines_pass2().
 template <typename R, bool HALF = false>
 hipError_t launch_pass2_impl(int L, const LaunchCfg& c, const cx<R>* Y, cx<R>* X, const DenseArgs<R>& a) {
   switch (L) {
 #define DD_CASE(LL)                                                        \
   case LL: {                                                               \
-    constexpr int RB = Geom<LL, (int)sizeof(R)>::lines_pass();             \
+    constexpr int RB = HALF ? Geom<LL, (int)sizeof(R)>::lines_pass()       \
+                            : Geom<LL, (int)sizeof(R)>::lines_pass2();     \
     return launch_kernel(k_pass2<R, LL, RB, HALF ? RB + 1 : RB>, c, Y, X, a); \
   }
     DD_POW2_LENGTHS(DD_CASE)

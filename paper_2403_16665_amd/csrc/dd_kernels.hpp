@@ -37,7 +37,8 @@ struct DenseArgs {
   int lines;          // lines per block: signals (single), columns (pass 1), rows (pass 2)
   int ntile;          // column tiles (pass 1) or row blocks (pass 2) per signal
   int jgroup, njg;    // j values per block and number of j groups (pass 1)
-  int pre_lds;        // pass 1: pre-twiddles of the block's j range staged in LDS
+  int pre_lds;        // pass 1: pre-twiddles of the block's j range staged in LDS: 1 whole rows,
+                      // 2 the entries n1 < TL and n1 = TL e of each row (their product is the factor)
   int q_lds;          // pass 1: W_{alpha N}^{j n2} of the block's j range and columns staged in LDS
                       // (a global load inside the j loop would wait for the previous j's stores:
                       // loads and stores share one in-order counter)
@@ -124,6 +125,12 @@ __host__ __device__ constexpr int pass2_lds_elems(int L, int RB, int rows = 0) {
 constexpr int LDS_PASS_MAX = 160 * 1024;
 
 constexpr int line_threads(int L) { return L / make_line_plan(L).EPT; }
+// LDS elements of pass 1's staged pre-twiddles for jg values of j: mode 1
+// whole rows W_{alpha N1}^{j n1}, mode 2 the entries n1 < TL and n1 = TL e
+// of each row (TL threads per line, EPT elements each), 0 none.
+constexpr int pass1_pre_elems(int mode, int jg, int L) {
+  return mode == 1 ? jg * L : mode == 2 ? jg * (line_threads(L) + L / line_threads(L)) : 0;
+}
 // Threads per line of the one-pass kernels (their plan: single_narrow).
 constexpr int single_line_threads(int L) { return L / make_line_plan(L, single_narrow(L)).EPT; }
 
@@ -146,6 +153,16 @@ struct Geom {
     return l;
   }
   static constexpr int BLOCK_PASS = TL * lines_pass();
+  // forward pass 2 alone: up to 1024 threads (its rows hold no tables, so a
+  // wave needs few registers), LDS within a CU -- the more rows per block,
+  // the longer the contiguous runs of its scattered output stores
+  static constexpr int lines_pass2() {
+    int l = 16;
+    if (TL * l < 256) l = 256 / TL;
+    while (l > 1 && TL * l > 1024) l /= 2;
+    while (l > 1 && CX * pass2_lds_elems(L, l) > LDS_PASS_MAX) l /= 2;
+    return l;
+  }
   // single pass: up to 256 threads (one line if TL >= 256)
   static constexpr int TLS = single_line_threads(L);
   static constexpr int lines_single() { return TLS >= 256 ? 1 : 256 / TLS; }
@@ -317,13 +334,24 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
   const int j1 = min(a.alpha, j0 + a.jgroup);
 
   // twiddle tables of this block into LDS (read every j; from L2 their latency
-  // sits on the critical path of each iteration)
+  // sits on the critical path of each iteration, and a global load inside
+  // the j loop waits for the previous j's stores: loads and stores share one
+  // in-order completion counter)
   for (int i = tid; i < TWN; i += NT) tws[i] = a.twL[i];
-  if (a.pre_lds) {
-    const int n = (j1 - j0) * L;
-    for (int i = tid; i < n; i += NT) pre[i] = a.twPre[j0 * L + i];
+  int pre_n = 0;
+  if (a.pre_lds == 1) {
+    // the block's rows of W_{alpha N1}^{j n1}, whole
+    pre_n = (j1 - j0) * L;
+    for (int i = tid; i < pre_n; i += NT) pre[i] = a.twPre[j0 * L + i];
+  } else if (a.pre_lds == 2) {
+    // columns too long to stage whole: the entries n1 = t ([j - j0][t]) and
+    // n1 = TL e ([j - j0][e]) of the same rows, whose product is the factor
+    const int na = (j1 - j0) * TL, nb = (j1 - j0) * EPT;
+    pre_n = na + nb;
+    for (int i = tid; i < na; i += NT) pre[i] = a.twPre[(j0 + i / TL) * L + i % TL];
+    for (int i = tid; i < nb; i += NT) pre[na + i] = a.twPre[(j0 + i / EPT) * L + TL * (i % EPT)];
   }
-  cx<R>* qs = pre + (a.pre_lds ? (j1 - j0) * L : 0);  // [j - j0][c] W_{alpha N}^{j n2} (when a.q_lds)
+  cx<R>* qs = pre + pre_n;  // [j - j0][c] W_{alpha N}^{j n2} (when a.q_lds)
   if (a.q_lds) {
     const int n = (j1 - j0) * C;
     for (int i = tid; i < n; i += NT) {
@@ -365,80 +393,108 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
   cx<R> wn2 = {(R)1, (R)0};
   if constexpr (REG_MIRROR && L >= 2)
     if (sym && colok) wn2 = cmul(a.twPost[N2 + n2], a.twPost[(L - 1) * N2 + n2]);
-  for (int j = j0; j < j1; ++j) {
-    if (sym && 2 * j > a.alpha) break;  // stored with their partners alpha - j
-    cx<R> v[EPT];
-    if (j == 0) {
+  // The j loop, in two instances.  Loads and stores share one in-order
+  // completion counter, so any global load the loop may issue (pre-twiddles
+  // or W_{alpha N}^{j n2} not staged in LDS) makes the compiler wait there
+  // for all earlier memory operations -- every store of the previous j --
+  // and, where the two kinds of operand merge, it waits in every case.  The
+  // LOCAL instance, taken when both are staged in LDS, reads only LDS inside
+  // the loop; the column's tables loaded before it are made complete first,
+  // so its stores stream out while the next transforms run.
+  auto jloop = [&](auto local_tag) {
+    constexpr bool LOCAL = decltype(local_tag)::value;
+    if constexpr (LOCAL) {
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) v[e] = xv[e];
-    } else if (a.pre_lds) {
-      const cx<R>* pj = pre + (j - j0) * L + t;               // W_{alpha N1}^{j n1}
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pj[TL * e]);
-    } else {
-      const cx<R>* __restrict__ pj = a.twPre + j * L + t;
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pj[TL * e]);
+      for (int e = 0; e < EPT; ++e) asm volatile("" : : "v"(pw[e].re), "v"(pw[e].im));
+      asm volatile("" : : "v"(wn2.re), "v"(wn2.im));
     }
-    line_fft<R, L, false>(v, t, ex, lay, tws);
-    if (colok) {
-      const cx<R> q = a.q_lds ? lds_read(qs + (j - j0) * C + c) : a.twQ[j * N2 + n2];  // W_{alpha N}^{j n2}
-      cx<R>* yj = ys + (int64_t)j * N2;
-      unsigned out_off_j = out_off;
-      if constexpr (REG_MIRROR) asm volatile("" : "+v"(out_off_j));
-      // rows kept: k1 < (hrows - j) / alpha, i.e. m1 = alpha k1 + j < hrows
-      const int klim = HALF && a.hrows > 0 ? (a.hrows - j + a.alpha - 1) / a.alpha : L;
-      // real input, every j in the block: the rows of jd = alpha - j too, at
-      // k1' = N1 - 1 - k1 = (TL - 1 - t) + TL (EPT - 1 - e) (the primary
-      // store's form with lane offset alpha N2 (TL - 1 - t) + n2), kept
-      // while below hrows
-      const bool mir = REG_MIRROR && sym && j >= 1 && 2 * j < a.alpha;
-      const int jd = a.alpha - j;
-      cx<R>* yd = ys + (int64_t)jd * N2;
-      unsigned off_d = (unsigned)(a.alpha * N2 * (TL - 1 - t) + n2);
-      if constexpr (REG_MIRROR) asm volatile("" : "+v"(off_d));
-      const int klim_d = mir ? (a.hrows - jd + a.alpha - 1) / a.alpha : 0;
-      cx<R> w = wn2;
-      if constexpr (REG_MIRROR && L == 1)
-        if (mir) w = cmul(q, a.q_lds ? lds_read(qs + (jd - j0) * C + c) : a.twQ[jd * N2 + n2]);
-      if (SPLIT && mir) {
+    auto qval = [&](int jj) -> cx<R> {  // W_{alpha N}^{jj n2}
+      if constexpr (LOCAL) return lds_read(qs + (jj - j0) * C + c);
+      else return a.q_lds ? lds_read(qs + (jj - j0) * C + c) : a.twQ[jj * N2 + n2];
+    };
+    for (int j = j0; j < j1; ++j) {
+      if (sym && 2 * j > a.alpha) break;  // stored with their partners alpha - j
+      cx<R> v[EPT];
+      if (j == 0) {
 #pragma unroll
-        for (int e = 0; e < EPT / 2; ++e) (yj + out_step * e)[out_off_j] = cmul(v[e], cmul(pw[e], q));
-        // conj(v pw q) w = conj(v) conj(pw) (conj(q) w)
-        const cx<R> qw = cmul(cconj(q), w);
+        for (int e = 0; e < EPT; ++e) v[e] = xv[e];
+      } else if (a.pre_lds == 1) {
+        const cx<R>* pj = pre + (j - j0) * L + t;               // W_{alpha N1}^{j n1}
 #pragma unroll
-        for (int e = EPT / 2; e < EPT; ++e)
-          (yd + out_step * (EPT - 1 - e))[off_d] = cmul(cconj(v[e]), cmul(cconj(pw[e]), qw));
+        for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pj[TL * e]);
+      } else if (LOCAL || a.pre_lds == 2) {
+        // W_{alpha N1}^{j (t + TL e)} = W_{alpha N1}^{j t} W_{alpha N1}^{j TL e}
+        const cx<R> pt = pre[(j - j0) * TL + t];
+        const cx<R>* pe = pre + (j1 - j0) * TL + (j - j0) * EPT;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], e == 0 ? pt : cmul(pt, pe[e]));
       } else {
+        const cx<R>* __restrict__ pj = a.twPre + j * L + t;
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          const cx<R> u = cmul(v[e], cmul(pw[e], q));
-          if (!HALF || t + TL * e < klim) (yj + out_step * e)[out_off_j] = u;
-          if constexpr (REG_MIRROR && !SPLIT)
-            if (L - 1 - t - TL * e < klim_d) (yd + out_step * (EPT - 1 - e))[off_d] = cmul(cconj(u), w);
-        }
+        for (int e = 0; e < EPT; ++e) v[e] = cmul(xv[e], pj[TL * e]);
       }
-    }
-    if constexpr (HALF && !REG_MIRROR) {
-      if (sym && j >= 1 && 2 * j < a.alpha) {
+      line_fft<R, L, false>(v, t, ex, lay, tws);
+      if (colok) {
+        const cx<R> q = qval(j);
+        cx<R>* yj = ys + (int64_t)j * N2;
+        unsigned out_off_j = out_off;
+        if constexpr (REG_MIRROR) asm volatile("" : "+v"(out_off_j));
+        // rows kept: k1 < (hrows - j) / alpha, i.e. m1 = alpha k1 + j < hrows
+        const int klim = HALF && a.hrows > 0 ? (a.hrows - j + a.alpha - 1) / a.alpha : L;
+        // real input, every j in the block: the rows of jd = alpha - j too, at
+        // k1' = N1 - 1 - k1 = (TL - 1 - t) + TL (EPT - 1 - e) (the primary
+        // store's form with lane offset alpha N2 (TL - 1 - t) + n2), kept
+        // while below hrows
+        const bool mir = REG_MIRROR && sym && j >= 1 && 2 * j < a.alpha;
         const int jd = a.alpha - j;
-        __syncthreads();  // the transform's last exchange has been read
+        cx<R>* yd = ys + (int64_t)jd * N2;
+        unsigned off_d = (unsigned)(a.alpha * N2 * (TL - 1 - t) + n2);
+        if constexpr (REG_MIRROR) asm volatile("" : "+v"(off_d));
+        const int klim_d = mir ? (a.hrows - jd + a.alpha - 1) / a.alpha : 0;
+        cx<R> w = wn2;
+        if constexpr (REG_MIRROR && L == 1)
+          if (mir) w = cmul(q, qval(jd));
+        if (SPLIT && mir) {
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) ex[lay(t + TL * e)] = v[e];
-        __syncthreads();
-        if (colok) {
-          const cx<R> q = a.q_lds ? lds_read(qs + (jd - j0) * C + c) : a.twQ[jd * N2 + n2];
-          cx<R>* yj = ys + (int64_t)jd * N2;
-          const int klim = (a.hrows - jd + a.alpha - 1) / a.alpha;
+          for (int e = 0; e < EPT / 2; ++e) (yj + out_step * e)[out_off_j] = cmul(v[e], cmul(pw[e], q));
+          // conj(v pw q) w = conj(v) conj(pw) (conj(q) w)
+          const cx<R> qw = cmul(cconj(q), w);
 #pragma unroll
-          for (int e = 0; e < EPT; ++e)
-            if (t + TL * e < klim)
-              (yj + out_step * e)[out_off] = cmul(cconj(ex[lay(L - 1 - t - TL * e)]), cmul(pw[e], q));
+          for (int e = EPT / 2; e < EPT; ++e)
+            (yd + out_step * (EPT - 1 - e))[off_d] = cmul(cconj(v[e]), cmul(cconj(pw[e]), qw));
+        } else {
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            const cx<R> u = cmul(v[e], cmul(pw[e], q));
+            if (!HALF || t + TL * e < klim) (yj + out_step * e)[out_off_j] = u;
+            if constexpr (REG_MIRROR && !SPLIT)
+              if (L - 1 - t - TL * e < klim_d) (yd + out_step * (EPT - 1 - e))[off_d] = cmul(cconj(u), w);
+          }
         }
-        __syncthreads();  // before the next transform's exchange
+      }
+      if constexpr (HALF && !REG_MIRROR) {
+        if (sym && j >= 1 && 2 * j < a.alpha) {
+          const int jd = a.alpha - j;
+          __syncthreads();  // the transform's last exchange has been read
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) ex[lay(t + TL * e)] = v[e];
+          __syncthreads();
+          if (colok) {
+            const cx<R> q = qval(jd);
+            cx<R>* yj = ys + (int64_t)jd * N2;
+            const int klim = (a.hrows - jd + a.alpha - 1) / a.alpha;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+              if (t + TL * e < klim)
+                (yj + out_step * e)[out_off] = cmul(cconj(ex[lay(L - 1 - t - TL * e)]), cmul(pw[e], q));
+          }
+          __syncthreads();  // before the next transform's exchange
+        }
       }
     }
-  }
+  };
+  if (a.pre_lds != 0 && a.q_lds) jloop(std::true_type{});
+  else jloop(std::false_type{});
   __syncthreads();  // LDS tables are rewritten by the next task of a persistent block
 }
 

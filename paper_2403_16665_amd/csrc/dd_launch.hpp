@@ -42,6 +42,7 @@ bool len_supported(int L);
 bool pass2_len_supported(int L);
 KGeom geom_single(int L, int rbytes);
 KGeom geom_pass(int L, int rbytes);
+KGeom geom_pass2(int L, int rbytes);  // forward pass 2 of complex input (lines_pass2)
 
 // Overloads per arithmetic type R (float, double) and input type (real R or
 // complex cx<R>); defined in dd_single_*.hip / dd_pass_*.hip.

@@ -72,6 +72,19 @@ KGeom geom_pass(int L, int rbytes) {
   }
 }
 
+KGeom geom_pass2(int L, int rbytes) {
+  switch (L) {
+#define DD_CASE(LL)                                                                                   \
+  case LL:                                                                                            \
+    if (rbytes == 4) return {Geom<LL, 4>::TL, Geom<LL, 4>::lines_pass2(), Geom<LL, 4>::TL * Geom<LL, 4>::lines_pass2()}; \
+    return {Geom<LL, 8>::TL, Geom<LL, 8>::lines_pass2(), Geom<LL, 8>::TL * Geom<LL, 8>::lines_pass2()};
+    DD_POW2_LENGTHS(DD_CASE)
+#undef DD_CASE
+    default:
+      return {0, 0, 0};
+  }
+}
+
 // Every instantiated length has a consistent radix plan.
 #define DD_CASE(LL) static_assert(line_plan_ok(LL) && line_plan_ok(LL, single_narrow(LL)), "bad line plan");
 DD_ALL_LENGTHS(DD_CASE)

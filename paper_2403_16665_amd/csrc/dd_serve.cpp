@@ -66,9 +66,6 @@ inline int variant_grid(int v, int full) {
   return v == GRID_VARIANTS - 1 ? full : std::min(full, 16 << (2 * v));
 }
 
-// Queued requests at or below which the head takes a slot alone, when there
-// are as many free slots (the admission policy's light-load rule).
-constexpr int SOLO_UPTO = 2;
 
 struct Slot {
   hipStream_t stream = nullptr;
@@ -172,12 +169,13 @@ bool launch_slot(dd_server* s, Slot& slot, std::unique_lock<std::mutex>& lk) {
     return true;
   };
   // light load: as long as every queued request can have a free slot of its
-  // own (at most SOLO_UPTO of them), the head goes alone; deterministic mode
-  // batches whatever is queued (results must not depend on the mix, so a
-  // request never takes the plain path instead)
+  // own, the head goes alone (requests then run concurrently, each at its
+  // solo latency; a batch only pays once requests outnumber the free
+  // slots); deterministic mode batches whatever is queued (results must not
+  // depend on the mix, so a request never takes the plain path instead)
   int free_slots = 0;
   for (const Slot& o : s->slots) free_slots += o.busy ? 0 : 1;
-  const int solo_upto = (s->cfg.flags & DD_SERVE_DETERMINISTIC) ? 0 : std::min(SOLO_UPTO, free_slots);
+  const int solo_upto = (s->cfg.flags & DD_SERVE_DETERMINISTIC) ? 0 : free_slots;
   admit_requests(s->pending, cap, plain_mode(s), [](const Req* r) { return r->kernel; }, reserve, take,
                  solo_upto);
   if (take.empty()) return false;
