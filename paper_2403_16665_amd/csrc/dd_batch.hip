@@ -77,10 +77,10 @@ __device__ __forceinline__ void run_pass2(const BatchItem* __restrict__ items, i
                                           int tid) {
   const BatchItem& it = items[item];
   DenseArgs<float> a = item_args(it);
-  a.lines = batch_lines(L);
+  a.lines = batch_lines2(L);
   a.ntile = it.ntile2;
   a.twL = it.twL2;
-  body_pass2<float, L, batch_lines(L)>(it.Y, it.X, a, sub, smem, tid);
+  body_pass2<float, L, batch_lines2(L)>(it.Y, it.X, a, sub, smem, tid);
 }
 
 // Persistent queue over the tasks of one launch (WHICH = 0: single-pass and
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(BATCH_THREADS) __attribute__((amdgpu_waves_per_eu(2
   batch_loop<0>(items, meta, head, smem);
 }
 
-__global__ __launch_bounds__(BATCH_THREADS) void k_batch_second(const BatchItem* __restrict__ items,
+__global__ __launch_bounds__(BATCH_THREADS2) void k_batch_second(const BatchItem* __restrict__ items,
                                                                 const BatchMeta* __restrict__ meta,
                                                                 unsigned* __restrict__ head) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -205,14 +205,14 @@ hipError_t launch_batch(const void* tab_host, void* tab_dev, int cap, unsigned* 
   hipLaunchKernelGGL(k_batch_first, dim3(grid1), dim3(BATCH_THREADS), lds1, s, items, meta, ctl);
   e = hipGetLastError();
   if (e != hipSuccess || grid2 <= 0) return e;
-  hipLaunchKernelGGL(k_batch_second, dim3(grid2), dim3(BATCH_THREADS), lds2, s, items, meta, ctl + 1);
+  hipLaunchKernelGGL(k_batch_second, dim3(grid2), dim3(BATCH_THREADS2), lds2, s, items, meta, ctl + 1);
   return hipGetLastError();
 }
 
 int batch_max_blocks_per_cu(int which, size_t lds) {
   int n = 0;
   const hipError_t e =
-      which ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_second, BATCH_THREADS, lds)
+      which ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_second, BATCH_THREADS2, lds)
             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_first, BATCH_THREADS, lds);
   if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;

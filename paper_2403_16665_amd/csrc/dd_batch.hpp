@@ -4,7 +4,8 @@
 // Every signal of a batch is an "item" with its own schedule (one pass, or
 // two passes N = N1 N2) and twiddle tables.  Its work is cut into block-sized
 // tasks: single-pass signals, pass-1 column tiles and pass-2 row blocks.  A
-// launch of k_batch runs a fixed grid of 256-thread blocks that take tasks
+// launch runs a fixed grid of blocks (256 threads in the first queue kernel,
+// 512 in the second) that take tasks
 // from a device queue until it is empty.  The single-pass and pass-1 tasks of
 // all items form the first launch, the pass-2 tasks the second, so the kernel
 // boundary publishes every scratch row before it is read and no block ever
@@ -47,6 +48,12 @@ __host__ __device__ constexpr int batch_code(int kind, int L) {
 
 // Lines per 256-thread block for a pass kernel of length L.
 __host__ __device__ constexpr int batch_lines(int L) { return BATCH_THREADS / line_threads(L); }
+// The pass-2 queue kernel runs blocks of 512 threads (its rows hold no
+// tables, so a wave needs few registers): rows per task for length L.  At
+// L = 512 that is 16 rows, so its scattered output stores are whole 128-byte
+// lines (with 8 rows, 64-byte pieces: measured 1.5x the time per byte).
+constexpr int BATCH_THREADS2 = 512;
+__host__ __device__ constexpr int batch_lines2(int L) { return BATCH_THREADS2 / line_threads(L); }
 // Thread groups sharing one single-pass signal of length L (each takes its
 // own values of j): as many as the block holds, but no more than alpha needs
 // (rounded up to a power of two) and no more than the LDS holds; 0 if not

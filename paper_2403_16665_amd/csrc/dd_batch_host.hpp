@@ -180,7 +180,7 @@ inline void fill_item(BatchItem& it, const dd_desc& d, const ClassTables& ct, cx
     it.code1 = batch_code(BK_SINGLE, sc.N1);
     it.code2 = -1;
   } else {
-    const int C = batch_lines(sc.N1), RB = batch_lines(sc.N2);
+    const int C = batch_lines(sc.N1), RB = batch_lines2(sc.N2);
     it.lines1 = C;
     it.ntile1 = (sc.N2 + C - 1) / C;
     it.jgroup = d.alpha;
@@ -210,12 +210,12 @@ inline size_t item_lds1(const BatchItem& it) {
   const int C = batch_lines(it.N1);
   return (size_t)pass1_lds_elems(it.N1, C, pass1_pre_elems(it.pre_lds, it.alpha, it.N1) + (it.q_lds ? it.alpha * C : 0)) * 8;
 }
-inline size_t item_lds2(const BatchItem& it) { return it.code2 < 0 ? 0 : lds_pass2(it.N2, batch_lines(it.N2), 4); }
+inline size_t item_lds2(const BatchItem& it) { return it.code2 < 0 ? 0 : lds_pass2(it.N2, batch_lines2(it.N2), 4); }
 
 // Largest pass-2 LDS of any compiled pass-2 length (a server's fixed launch).
 inline size_t batch_lds2_max() {
   size_t m = 0;
-#define DD_L2(LL) m = std::max(m, lds_pass2(LL, batch_lines(LL), 4));
+#define DD_L2(LL) m = std::max(m, lds_pass2(LL, batch_lines2(LL), 4));
   DD_BATCH_P2(DD_L2)
 #undef DD_L2
   return m;
