@@ -539,13 +539,16 @@ def run_inverse(args):
     T, M = N * dt, alpha * N
     x = np.stack([siggen.tones_complex(g, N, dt) for g in siggen.rngs(1, batch)])
     xd = torch.from_numpy(x).cuda()
-    if args.tune_db and os.path.exists(args.tune_db):
-        dd.dense_dft_tune_load(args.tune_db)  # the schedule of an earlier run, no tuner launches
-    elif args.tune:
-        dd.dense_dft_tune(N, alpha, batch, dd.DD_C64)
-        if args.tune_db:
-            dd.dense_dft_tune_save(args.tune_db)
-    plan = dd.dense_dft_plan(N, alpha, T, batch, dd.DD_C64)
+    if args.sched:
+        plan = dd.dense_dft_plan_sched(N, alpha, T, batch, dd.DD_C64, parse_sched(args.sched))
+    else:
+        if args.tune_db and os.path.exists(args.tune_db):
+            dd.dense_dft_tune_load(args.tune_db)  # the schedule of an earlier run, no tuner launches
+        elif args.tune:
+            dd.dense_dft_tune(N, alpha, batch, dd.DD_C64)
+            if args.tune_db:
+                dd.dense_dft_tune_save(args.tune_db)
+        plan = dd.dense_dft_plan(N, alpha, T, batch, dd.DD_C64)
     X = torch.empty(batch, M, dtype=torch.complex64, device="cuda")
     dd.dense_dft_exec(plan, xd, X)
     back = torch.empty(batch, N, dtype=torch.complex64, device="cuda")
@@ -681,8 +684,8 @@ def main():
                          "from PATH if it exists, else tune and save it there (profiling runs then "
                          "time the same schedules)")
     ap.add_argument("--sched", default="", metavar="N1xN2[:JGROUP[:CHUNK]]",
-                    help="plain workloads: run this two-pass schedule instead of tuning (profiles name "
-                         "their schedule this way, so that a re-take times the same launches)")
+                    help="plain and inverse workloads: run this two-pass schedule instead of tuning "
+                         "(profiles name their schedule this way, so that a re-take times the same launches)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="instead of the transform, run --steps plain device copies of MIB MiB "
                          "(calibrates the profiler's HBM byte counters)")
@@ -873,9 +876,12 @@ def run_plain(args, name, oracle_signals=0):
         # the same samples through the complex path, which transforms every
         # scratch row instead of the Hermitian half
         xc = xd.to(torch.complex64)
-        if args.tune:
-            dd.dense_dft_tune(N, alpha, batch, dd.DD_C64)
-        plan_c = dd.dense_dft_plan(N, alpha, T, batch, dd.DD_C64)
+        if args.sched:
+            plan_c = dd.dense_dft_plan_sched(N, alpha, T, batch, dd.DD_C64, parse_sched(args.sched))
+        else:
+            if args.tune:
+                dd.dense_dft_tune(N, alpha, batch, dd.DD_C64)
+            plan_c = dd.dense_dft_plan(N, alpha, T, batch, dd.DD_C64)
         Xc = torch.empty_like(Xd)
         for _ in range(args.warmup):
             dd.dense_dft_exec(plan_c, xc, Xc, stream=sp)
