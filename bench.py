@@ -124,7 +124,7 @@ def tune_classes(dd, classes, batch_kernel=True, plain_batch=1, dtypes=None):
     return out
 
 
-def precision_errors(dd, xd, Xd, N, alpha, T):
+def precision_errors(dd, xd, Xd, N, alpha, T, sched):
     """The precision form: relative L2 error against the FP64 oracle on the
     workload's 16384 seeded bins (tests/golden fixture written by the oracle)
     with FP64-generated twiddles (Xd, the timed output) and with the
@@ -134,7 +134,8 @@ def precision_errors(dd, xd, Xd, N, alpha, T):
     fx = np.load(path, allow_pickle=False)
     bins, ref = fx["bins"], fx["X"]
     idx = torch.from_numpy(bins).to(Xd.device)
-    p32 = dd.dense_dft_plan(N, alpha, T, 1, dd.DD_C64, dd.DD_TWIDDLE_FP32)
+    # the FP32-twiddle variant under the timed plan's schedule
+    p32 = dd.dense_dft_plan_sched(N, alpha, T, 1, dd.DD_C64, dd.make_sched(**sched), dd.DD_TWIDDLE_FP32)
     X32 = torch.empty_like(Xd)
     dd.dense_dft_exec(p32, xd, X32)
     torch.cuda.synchronize()
@@ -871,7 +872,7 @@ def run_plain(args, name, oracle_signals=0):
     if traffic:
         result["roofline"]["amplification"] = traffic / b_alg   # measured HBM bytes / algorithmic
     if name == "precision":
-        result["precision"] = precision_errors(dd, xd, Xd, N, alpha, T)
+        result["precision"] = precision_errors(dd, xd, Xd, N, alpha, T, dd.dense_dft_plan_get_sched(plan))
     if name == "real_f32":
         # the same samples through the complex path, which transforms every
         # scratch row instead of the Hermitian half
