@@ -389,19 +389,30 @@ def dense_dft_tune_entries():
 
 # --- many signals of uneven N and alpha in one persistent launch ---
 class Batch:
-    """Owning handle of a dd_batch_t."""
+    """Owning handle of a dd_batch_t.  It keeps the tensors its descriptors
+    name, so that they outlive every execution the plan may still make."""
 
     _destroy = _lib.dense_dft_batch_destroy
 
-    def __init__(self, handle, count):
+    def __init__(self, handle, count, tensors=()):
         self.handle = handle
         self.count = count
+        self.tensors = list(tensors)
 
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:
             self._destroy(h)
             self.handle = None
+
+
+def _desc_tensors(descs):
+    """The tensors named by (N, alpha, T, dtype, x, X) descriptors."""
+    out = []
+    for d in descs:
+        if not isinstance(d, dd_desc):
+            out += [t for t in d[4:6] if t is not None]
+    return out
 
 
 def _desc_array(descs):
@@ -417,21 +428,28 @@ def _desc_array(descs):
 
 
 def dense_dft_batch_plan(descs, flags: int = DD_TWIDDLE_FP64) -> Batch:
+    """Plan one persistent launch over the descriptors (N, alpha, T, dtype, x, X).
+    The returned Batch keeps x and X alive (a dd_desc passes raw addresses, and
+    its buffers are the caller's to keep)."""
+    descs = list(descs)
     arr, n = _desc_array(descs)
     h = _vp()
     _check(_lib.dense_dft_batch_plan(ctypes.byref(h), arr, n, int(flags)), "dense_dft_batch_plan")
-    return Batch(h, n)
+    return Batch(h, n, _desc_tensors(descs))
 
 
 def dense_dft_batch_plan_sched(descs, sched: dd_sched, flags: int = DD_TWIDDLE_FP64) -> Batch:
+    descs = list(descs)
     arr, n = _desc_array(descs)
     h = _vp()
     _check(_lib.dense_dft_batch_plan_sched(ctypes.byref(h), arr, n, int(flags), ctypes.byref(sched)),
            "dense_dft_batch_plan_sched")
-    return Batch(h, n)
+    return Batch(h, n, _desc_tensors(descs))
 
 
 def dense_dft_batch_exec(batch: Batch, stream=None) -> None:
+    """Enqueue the batch on ``stream`` (default: torch's current stream); the
+    inputs must have been written by work ordered before it on that stream."""
     if stream is None:
         import torch
         stream = torch.cuda.current_stream().cuda_stream
@@ -439,8 +457,13 @@ def dense_dft_batch_exec(batch: Batch, stream=None) -> None:
 
 
 def dense_dft_batch_set_buffers(batch: Batch, descs) -> None:
+    """New buffers for the next executions (same shapes); the batch then keeps
+    the new tensors instead of the old ones.  Executions already enqueued
+    still use the old buffers: synchronise their stream before freeing those."""
+    descs = list(descs)
     arr, n = _desc_array(descs)
     _check(_lib.dense_dft_batch_set_buffers(batch.handle, arr, n), "dense_dft_batch_set_buffers")
+    batch.tensors = _desc_tensors(descs)
 
 
 def dense_dft_batch_status(batch: Batch) -> int:
@@ -527,6 +550,7 @@ class Server:
     def __init__(self, handle, cfg):
         self.handle = handle
         self.cfg = cfg
+        self.pending = {}   # ticket -> the tensors of its request, until its result is taken
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -568,7 +592,13 @@ def _one_desc(d, what: str = "request") -> dd_desc:
 
 def dense_dft_submit(server: Server, desc, t_arrival_ns: int | None = None) -> int:
     """Queue one request (N, alpha, T, dtype, x_tensor, X_tensor); returns its ticket.
-    Raises DenseDFTError (status DD_ERR_BUSY / DD_ERR_TOO_LARGE / ...) on refusal."""
+    Raises DenseDFTError (status DD_ERR_BUSY / DD_ERR_TOO_LARGE / ...) on refusal.
+
+    The server keeps x and X alive until the ticket's result is taken
+    (dense_dft_wait, or dense_dft_poll once done).  Its streams are not ordered
+    after torch's: x must already hold its samples (synchronise the stream
+    that wrote it before submitting), and X is complete when the result says
+    done."""
     d = _one_desc(desc)
     t = _u64()
     if t_arrival_ns is None:
@@ -576,6 +606,8 @@ def dense_dft_submit(server: Server, desc, t_arrival_ns: int | None = None) -> i
     else:
         rc = _lib.dense_dft_submit_at(server.handle, ctypes.byref(d), int(t_arrival_ns), ctypes.byref(t))
     _check(rc, "dense_dft_submit")
+    if not isinstance(desc, dd_desc):
+        server.pending[int(t.value)] = _desc_tensors([desc])
     return int(t.value)
 
 
@@ -587,11 +619,15 @@ def dense_dft_submit_at(server: Server, desc, t_arrival_ns: int) -> int:
 def dense_dft_submit_many_at(server: Server, descs, t_arrival_ns):
     """Open-loop replay: queue descs[i] at host time t_arrival_ns[i] (non-decreasing,
     dense_dft_clock_ns scale); returns the tickets.  Blocks until the last is queued."""
+    descs = list(descs)
     arr, n = _desc_array(descs)
     ts = (_u64 * n)(*[int(t) for t in t_arrival_ns])
     tk = (_u64 * n)()
     done = ctypes.c_int32()
     rc = _lib.dense_dft_submit_many_at(server.handle, arr, ts, n, tk, ctypes.byref(done))
+    for i in range(done.value):
+        if not isinstance(descs[i], dd_desc):
+            server.pending[int(tk[i])] = _desc_tensors([descs[i]])
     _check(rc, f"dense_dft_submit_many_at (queued {done.value} of {n})")
     return [int(t) for t in tk]
 
@@ -608,12 +644,14 @@ def dense_dft_poll(server: Server, ticket: int):
     if rc == DD_ERR_BUSY:
         return None
     _check(rc, "dense_dft_poll")
+    server.pending.pop(int(ticket), None)
     return _result_dict(r)
 
 
 def dense_dft_wait(server: Server, ticket: int, timeout_us: int = -1) -> dict:
     r = dd_result()
     _check(_lib.dense_dft_wait(server.handle, int(ticket), int(timeout_us), ctypes.byref(r)), "dense_dft_wait")
+    server.pending.pop(int(ticket), None)
     return _result_dict(r)
 
 
@@ -631,6 +669,7 @@ def dense_dft_server_destroy(server: Server) -> None:
     if server.handle:
         _check(_lib.dense_dft_server_destroy(server.handle), "dense_dft_server_destroy")
         server.handle = None
+        server.pending.clear()
 
 
 def dense_dft_clock_ns() -> int:
