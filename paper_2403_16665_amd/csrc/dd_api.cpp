@@ -52,6 +52,8 @@ struct dd_plan {
   // transforms them in blocks of p2_lines + 1 rows (when those fit the LDS)
   bool p2_half = false;
   size_t p2h_lds = 0;
+  // the scratch: rows m1 of y_row elements (N2 and a pad), y_sig per signal
+  int64_t y_row = 1, y_sig = 1;
   // inverse pass B (every j per block): pre-twiddles staged in LDS, its LDS
   int inv_pre_lds = 0;
   size_t inv_p1_lds = 0;
@@ -220,8 +222,12 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
   p->p2f_lds = lds_pass2((int)N2, g2f.lines, p->rbytes);
   p->p2h_lds = lds_pass2((int)N2, g2.lines, p->rbytes, g2.lines + 1);
   p->p2_half = (p->dtype == DD_F32 || p->dtype == DD_F64) && p->p2h_lds <= (size_t)LDS_PASS_MAX;
+  // scratch rows padded off a power-of-two stride (scratch_row_pad)
+  p->y_row = N2 + scratch_row_pad(N2, alpha, (int)cx_bytes(p));
+  p->y_sig = (int64_t)alpha * N1 * p->y_row;
+  (void)M;
   // signals per pass pair: by default the scratch of one chunk within 128 MiB
-  const size_t per_sig = (size_t)M * cx_bytes(p);
+  const size_t per_sig = (size_t)p->y_sig * cx_bytes(p);
   int64_t chunk = sc.chunk;
   if (chunk <= 0) chunk = (int64_t)((128u << 20) / per_sig);
   if (chunk < 1) chunk = 1;
@@ -570,6 +576,8 @@ dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s
     a1.batch = nb;
     a1.x_stride = p->N;
     a1.y_stride = M;
+    a1.ysig = p->y_sig;
+    a1.yrow = (int)p->y_row;
     a1.N1 = (int)p->N1;
     a1.N2 = (int)p->N2;
     a1.alpha = p->alpha;
@@ -745,7 +753,7 @@ dd_status dense_dft_exec_static(dd_plan_t p, const void* x, void* X, void* strea
   if (p->passes == 1) return exec_dispatch(p, x, X, nullptr, s, p->chunk);
   // two passes: as many signals per pass pair as the array holds, at most
   // the plan's own chunk (within one dispatch's grid)
-  const size_t per_sig = (size_t)p->alpha * p->N * out_cx;
+  const size_t per_sig = (size_t)p->y_sig * out_cx;
   if (per_sig > STATIC_SCRATCH_BYTES) return DD_ERR_TOO_LARGE;
   int64_t chunk = (int64_t)(STATIC_SCRATCH_BYTES / per_sig);
   if (chunk > p->chunk) chunk = p->chunk;

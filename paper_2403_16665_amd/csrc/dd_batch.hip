@@ -36,6 +36,8 @@ __device__ __forceinline__ DenseArgs<float> item_args(const BatchItem& it) {
   a.batch = 1;
   a.x_stride = it.N;
   a.y_stride = (int64_t)it.alpha * it.N;
+  a.ysig = (int64_t)it.alpha * it.N;
+  a.yrow = it.N2;
   a.N1 = it.N1;
   a.N2 = it.N2;
   a.alpha = it.alpha;

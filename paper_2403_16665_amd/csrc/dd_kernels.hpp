@@ -32,7 +32,10 @@ template <typename R>
 struct DenseArgs {
   int64_t batch;      // signals handled by this launch
   int64_t x_stride;   // input elements between signals
-  int64_t y_stride;   // complex elements between signals of the output / scratch
+  int64_t y_stride;   // complex elements between signals of the output
+  int64_t ysig;       // two passes: complex elements between signals of the scratch
+  int yrow;           // two passes: complex elements between scratch rows m1 (N2, or N2 and a pad
+                      // that keeps the rows of a wavefront's stores off one memory channel)
   int N1, N2, alpha;
   int lines;          // lines per block: signals (single), columns (pass 1), rows (pass 2)
   int ntile;          // column tiles (pass 1) or row blocks (pass 2) per signal
@@ -377,9 +380,10 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
 #pragma unroll
   for (int e = 0; e < EPT; ++e) xv[e] = cscale(xv[e], a.scale);
   __syncthreads();
-  const unsigned out_off = (unsigned)(a.alpha * N2 * t + n2);  // lane part of (alpha k1 + j) N2 + n2
-  const unsigned out_step = (unsigned)(a.alpha * N2 * TL);
-  cx<R>* ys = Y + sig * a.y_stride;
+  const int S = a.yrow;  // scratch row stride
+  const unsigned out_off = (unsigned)(a.alpha * S * t + n2);  // lane part of (alpha k1 + j) S + n2
+  const unsigned out_step = (unsigned)(a.alpha * S * TL);
+  cx<R>* ys = Y + sig * a.ysig;
   constexpr bool REG_MIRROR = HALF && sizeof(R) == 4 && L % 5 != 0;
   // SPLIT: with N1 and EPT even and hrows = alpha N1 / 2 + 1, every mirrored
   // j keeps the rows k1 < N1 / 2 (elements e < EPT / 2) and its partner
@@ -436,19 +440,19 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
       line_fft<R, L, false>(v, t, ex, lay, tws);
       if (colok) {
         const cx<R> q = qval(j);
-        cx<R>* yj = ys + (int64_t)j * N2;
+        cx<R>* yj = ys + (int64_t)j * S;
         unsigned out_off_j = out_off;
         if constexpr (REG_MIRROR) asm volatile("" : "+v"(out_off_j));
         // rows kept: k1 < (hrows - j) / alpha, i.e. m1 = alpha k1 + j < hrows
         const int klim = HALF && a.hrows > 0 ? (a.hrows - j + a.alpha - 1) / a.alpha : L;
         // real input, every j in the block: the rows of jd = alpha - j too, at
         // k1' = N1 - 1 - k1 = (TL - 1 - t) + TL (EPT - 1 - e) (the primary
-        // store's form with lane offset alpha N2 (TL - 1 - t) + n2), kept
+        // store's form with lane offset alpha S (TL - 1 - t) + n2), kept
         // while below hrows
         const bool mir = REG_MIRROR && sym && j >= 1 && 2 * j < a.alpha;
         const int jd = a.alpha - j;
-        cx<R>* yd = ys + (int64_t)jd * N2;
-        unsigned off_d = (unsigned)(a.alpha * N2 * (TL - 1 - t) + n2);
+        cx<R>* yd = ys + (int64_t)jd * S;
+        unsigned off_d = (unsigned)(a.alpha * S * (TL - 1 - t) + n2);
         if constexpr (REG_MIRROR) asm volatile("" : "+v"(off_d));
         const int klim_d = mir ? (a.hrows - jd + a.alpha - 1) / a.alpha : 0;
         cx<R> w = wn2;
@@ -481,7 +485,7 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
           __syncthreads();
           if (colok) {
             const cx<R> q = qval(jd);
-            cx<R>* yj = ys + (int64_t)jd * N2;
+            cx<R>* yj = ys + (int64_t)jd * S;
             const int klim = (a.hrows - jd + a.alpha - 1) / a.alpha;
 #pragma unroll
             for (int e = 0; e < EPT; ++e)
@@ -524,8 +528,8 @@ __device__ __forceinline__ void body_pass2(const cx<R>* __restrict__ Y, cx<R>* _
   const int prim = a.hrows > 0 ? rows - (a.hrows - 1) : rows;  // rows stored as they are
   const int m1 = rb * RB + r;
   const bool ok = m1 < lim;
-  const cx<R>* ys = Y + sig * a.y_stride + (int64_t)rb * RB * L;
-  const unsigned row_off = (unsigned)(r * L + t);
+  const cx<R>* ys = Y + sig * a.ysig + (int64_t)rb * RB * a.yrow;
+  const unsigned row_off = (unsigned)(r * a.yrow + t);
   cx<R> v[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) v[e] = ok ? (ys + TL * e)[row_off] : cx<R>{(R)0, (R)0};

@@ -85,6 +85,22 @@ inline size_t lds_pass2(int L, int lines, int rbytes, int rows = 0) {
   return (size_t)pass2_lds_elems(L, lines, rows) * 2 * rbytes;
 }
 
+// Pad of the two-pass scratch rows (elements).  The lanes of a pass-1
+// wavefront store rows alpha * (N2 + pad) elements apart; with whole rows of
+// N2 that stride is a power of two, and for long row groups every store of
+// the wavefront falls on one memory channel (measured for the scratch writes
+// of 2^22 x alpha 16 alone: 16-byte pieces 630 -> 234 us, 32-byte pieces
+// 531 -> 171 us, 64-byte pieces 241 -> 137 us with 512 bytes per row; row
+// groups below 64 KiB showed no effect).  Only rows of at least 4 KiB get
+// the pad, so it adds at most 1/8 to the scratch.
+inline int64_t scratch_row_pad(int64_t N2, int alpha, int cx_bytes) {
+  const int64_t rb = N2 * cx_bytes;
+  return rb >= 4096 && alpha * rb >= 64 * 1024 ? 512 / cx_bytes : 0;
+}
+// Scratch bytes that one signal's two-pass execution needs at most, whatever
+// its split, given its unpadded spectrum of `bytes`.
+inline size_t scratch_bytes_bound(size_t bytes) { return bytes >= 64 * 1024 ? bytes + bytes / 8 : bytes; }
+
 // A dispatch's grid size is a 32-bit count of work-items; launches are kept
 // below 2^31 of them, and larger batches are split over several launches.
 constexpr int64_t MAX_LAUNCH_ITEMS = 0x7fffffff;

@@ -370,10 +370,10 @@ dd_status classify_shape(const dd_server* s, int64_t N, int alpha, double T, dd_
   const size_t M = (size_t)alpha * N;
   r->kernel = !plain_mode(s) && (dtype == DD_F32 || dtype == DD_C64) &&
               (s->cfg.batch_max_bins < 0 || (int64_t)M <= s->cfg.batch_max_bins) && batch_schedule(N, alpha, &r->sc);
-  // at most one spectrum of scratch in the request's precision: a two-pass
-  // kernel item's, or a plain execution's (which a kernel request alone in
-  // its batch may become)
-  r->scratch = M * batch_out_elem(dtype);
+  // scratch for a two-pass kernel item (one spectrum in the request's
+  // precision) or a plain execution, which a kernel request alone in its
+  // batch may become (its rows may be padded: at most 1/8 more)
+  r->scratch = scratch_bytes_bound(M * batch_out_elem(dtype));
   r->footprint = (size_t)N * batch_in_elem(dtype) + M * batch_out_elem(dtype) + round_up(r->scratch, POOL_ALIGN);
   return DD_OK;
 }

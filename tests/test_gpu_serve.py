@@ -277,3 +277,31 @@ def test_class_schedule_survives_a_tuning_change(oracle_mod, tmp_path):
     for (n, a, c, x), X in zip(reqs, Xs):
         ref = oracle_mod.alpha_dft(x, a, n * 1e-3)
         assert_close(X.cpu().numpy(), ref, "f32", f"N={n} alpha={a}")
+
+
+def test_plain_workspace_within_the_servers_reservation():
+    """The server reserves, for a request of alpha N bins, the spectrum's
+    bytes plus 1/8 when the spectrum takes at least 64 KiB (the most that
+    padded scratch rows add); a plain execution of one signal, which any
+    request may become, needs no more under any schedule.  Also pins that the
+    rows of long row groups are padded (2^22 x alpha 16) and short ones not."""
+    import paper_2403_16665_amd as dd
+    shapes = [(262144, 16), (262144, 2), (131072, 8), (65536, 8), (4194304, 16), (1 << 20, 4), (3 * 4096, 16)]
+    for N, a in shapes:
+        for code, elem in ((dd.DD_C64, 8), (dd.DD_F32, 8), (dd.DD_C128, 16)):
+            spec = a * N * elem
+            bound = spec + spec // 8 if spec >= 64 * 1024 else spec
+            for sc in dd.dense_dft_sched_candidates(N, a, 1, code):
+                if sc.passes != 2:
+                    continue
+                try:
+                    plan = dd.dense_dft_plan_sched(N, a, N * 1e-3, 1, code, sc, dd.DD_NO_WORKSPACE)
+                except dd.DenseDFTError:
+                    continue   # a split the kernels of this precision do not hold
+                ws = dd.dense_dft_workspace_size(plan)
+                assert spec <= ws <= bound, (N, a, code, sc.N1, sc.N2, ws, bound)
+                if (N, a, code) == (4194304, 16, dd.DD_C64) and sc.N2 == 1024:
+                    assert ws == a * sc.N1 * (sc.N2 + 64) * 8   # rows padded by 512 bytes
+                if (N, a, elem) == (65536, 8, 8) and sc.N2 <= 512:
+                    assert ws == spec                          # short row groups unpadded
+                dd.dense_dft_destroy(plan)
