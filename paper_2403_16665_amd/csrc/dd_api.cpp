@@ -243,16 +243,23 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
   }
   p->p1_jgroup = jg;
   p->p1_njg = (alpha + jg - 1) / jg;
-  // stage the block's pre-twiddles in LDS when whole rows take at most 16 KiB.
-  // (Their two factors, mode 2, were measured slower for the long columns that
-  // need them here: 2^22 x alpha 16, pass 1 at N1 = 4096 337 -> 512 us.  Its
-  // global loads hold each j's stores back until the previous j's are out,
-  // which keeps its scattered 16-byte stores merging in the L2.)
+  // stage the block's pre-twiddles in LDS: whole rows when they take at most
+  // 16 KiB, else their two factors (mode 2) when that costs no block of
+  // residency per CU.  The j loop then reads no global memory, so each j's
+  // stores stream out while the next j is transformed (2^22 x alpha 16,
+  // padded scratch rows: pass 1 at N1 = 4096 319 -> 284 us, at 2048
+  // 233 -> 189 us; with unpadded rows the overlapping stores of successive
+  // j fell on one memory channel and it was slower, 337 -> 512 us).
   const size_t pre_bytes = (size_t)jg * N1 * cx_bytes(p);
   const size_t cu_lds = 160 * 1024;
   p->p1_pre_lds = pre_bytes <= 16 * 1024 &&
                   lds_pass1((int)N1, g1.lines, p->rbytes, pass1_pre_elems(1, jg, (int)N1)) <= (size_t)LDS_PASS_MAX
                       ? 1 : 0;
+  if (!p->p1_pre_lds) {
+    const size_t l0 = lds_pass1((int)N1, g1.lines, p->rbytes, 0);
+    const size_t l2 = lds_pass1((int)N1, g1.lines, p->rbytes, pass1_pre_elems(2, jg, (int)N1));
+    if (l2 <= (size_t)LDS_PASS_MAX && cu_lds / l2 == cu_lds / l0) p->p1_pre_lds = 2;
+  }
   p->p1_lds = lds_pass1((int)N1, g1.lines, p->rbytes, pass1_pre_elems(p->p1_pre_lds, jg, (int)N1));
   // and the block's W_{alpha N}^{j n2} when they take at most 4 KiB and do
   // not cost a block of residency per CU

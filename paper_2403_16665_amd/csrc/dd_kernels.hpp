@@ -543,11 +543,21 @@ __device__ __forceinline__ void body_pass2(const cx<R>* __restrict__ Y, cx<R>* _
   cx<R>* xs = X + sig * a.y_stride;
   constexpr int total = RB * L;
   constexpr int NT = ROWS * TL;
+  // Runs of RB bins shorter than a 128-byte line are completed by the
+  // neighbouring block (the same XCD): those stores stay cached so that the
+  // L2 merges the two halves (non-temporal, each half went to memory as a
+  // partial line: 2^22 x alpha 16, pass 2 at N2 = 2048 450 -> 348 us, at
+  // N2 = 4096 1209 -> 540 us).
+  constexpr bool WHOLE = RB * (int)sizeof(cx<R>) >= 128;
+  auto put = [&](cx<R>* p, cx<R> v) {
+    if constexpr (WHOLE) store_out(p, v);
+    else *p = v;
+  };
 #pragma unroll 4
   for (int i = tid; i < total; i += NT) {
     const int rr = i % RB, k2 = i / RB;
     const int m = rb * RB + rr;
-    if (m < prim) store_out(xs + (int64_t)m + (int64_t)rows * k2, ex[k2 * SR + rr]);
+    if (m < prim) put(xs + (int64_t)m + (int64_t)rows * k2, ex[k2 * SR + rr]);
   }
   if (a.hrows > 0) {
     // conjugate mirrors: consecutive i -> consecutive target rows rows - m
@@ -555,7 +565,7 @@ __device__ __forceinline__ void body_pass2(const cx<R>* __restrict__ Y, cx<R>* _
     for (int i = tid; i < total; i += NT) {
       const int rr = RB - 1 - i % RB + (ROWS - RB), kk = i / RB;
       const int m = rb * RB + rr;
-      if (m >= 1 && m < lim) store_out(xs + (int64_t)(rows - m) + (int64_t)rows * kk, cconj(ex[(L - 1 - kk) * SR + rr]));
+      if (m >= 1 && m < lim) put(xs + (int64_t)(rows - m) + (int64_t)rows * kk, cconj(ex[(L - 1 - kk) * SR + rr]));
     }
   }
   __syncthreads();  // the staging buffer is reused by the next task of a persistent block
