@@ -134,9 +134,12 @@ dd_status dense_dft_plan(dd_plan_t *out, int64_t N, int32_t alpha, double T,
 dd_status dense_dft_plan_decimated(dd_plan_t *out, int64_t N, int32_t p, double T,
                                    int64_t batch, dd_dtype dtype, uint32_t flags);
 
-/* Bytes of device scratch one execution needs (0 for single-pass plans).
- * The plan owns a default workspace of this size unless it was created with
- * DD_NO_WORKSPACE. */
+/* Bytes of device scratch one execution needs (0 for single-pass plans):
+ * chunk signals of alpha*N1 rows each.  A row holds N2 elements, plus 512
+ * bytes when a row takes at least 4 KiB and alpha rows at least 64 KiB (the
+ * pad keeps a wavefront's stores off one memory channel), so one signal
+ * needs at most 9/8 of its alpha*N output elements.  The plan owns a default
+ * workspace of this size unless it was created with DD_NO_WORKSPACE. */
 dd_status dense_dft_workspace_size(dd_plan_t plan, size_t *bytes);
 
 /* Enqueue the transform of all `batch` signals of the plan on `stream`.
@@ -172,7 +175,8 @@ dd_status dense_dft_exec(dd_plan_t plan, const void *x, void *X,
  * DD_NO_WORKSPACE to allocate no workspace at all.
  *   plan, x, X, stream : as dense_dft_exec.
  * Errors: as dense_dft_exec; DD_ERR_TOO_LARGE when one signal's scratch
- *         (alpha*N output elements) exceeds DD_STATIC_SCRATCH_BYTES;
+ *         (alpha*N output elements, and the row pad of
+ *         dense_dft_workspace_size) exceeds DD_STATIC_SCRATCH_BYTES;
  *         DD_ERR_UNSUPPORTED for alpha = 1/p plans (dense_dft_plan_decimated). */
 #define DD_STATIC_SCRATCH_BYTES (64u << 20)
 dd_status dense_dft_exec_static(dd_plan_t plan, const void *x, void *X, void *stream);
@@ -409,7 +413,9 @@ dd_status dense_dft_exec_many(const dd_desc *descs, int32_t count,
  * the plain ones, as many as the batch size and the memory budget admit,
  * and launches them as one batch.  A request alone in its batch runs as a
  * plain execution too, unless DD_SERVE_DETERMINISTIC.  A request's footprint is its input and
- * output bytes plus its scratch; the footprints of admitted, unfinished requests never sum past
+ * output bytes plus its scratch (its output's bytes, plus 1/8 when they reach
+ * 64 KiB: the most a plain execution's padded rows need, see
+ * dense_dft_workspace_size); the footprints of admitted, unfinished requests never sum past
  * hbm_budget_bytes.  Each request is the transform of one dd_desc (the
  * problem of Section 2 for one signal); x and X are the caller's device
  * buffers and must stay allocated and untouched until the request is done.
