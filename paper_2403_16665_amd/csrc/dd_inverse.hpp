@@ -73,6 +73,14 @@ __device__ __forceinline__ void body_single_inv(const cx<R>* __restrict__ X, cx<
   }
 }
 
+// Which pass applies the inter-pass twiddle W_{alpha N}^{m1 n2}.  In single
+// precision pass B, as it reads G back (pass A would load 2 x EPT table
+// entries per thread, twice its data loads; pass B holds W_N^{k1 n2} for its
+// column across every j, as the forward pass 1 does).  In double precision
+// pass A: held in pass B the factors spill registers.
+template <typename R>
+__host__ __device__ constexpr bool inv_twiddle_in_b() { return sizeof(R) == 4; }
+
 // Pass A: block = (signal, RB consecutive rows m1).  The RB x N2 values
 // X_{m1 + alpha N1 k2} of its rows are read as runs of RB bins (the forward
 // pass 2's store pattern) through an LDS transpose; thread (t, r) then owns
@@ -105,54 +113,47 @@ __device__ __forceinline__ void body_passA(const cx<R>* __restrict__ X, cx<R>* _
 #pragma unroll
   for (int u = 0; u < EPT; ++u)
     g[u] = mrow < rows ? load_once(xs + (int64_t)mrow + (int64_t)rows * (kb + u * TL)) : cx<R>{(R)0, (R)0};
-  // the inter-pass twiddle of this thread's row, W_{alpha N}^{m1 n2} =
-  // W_N^{k1 n2} W_{alpha N}^{j n2} with m1 = alpha k1 + j.  In single
-  // precision its loads go out with the gather, so one memory latency covers
-  // both, and only the product stays live through the FFT; in double the
-  // extra registers would spill, so they are loaded after the FFT.
-  constexpr bool EARLY = sizeof(R) == 4;
-  const int k1 = ok ? m1 / a.alpha : 0, j = ok ? m1 - k1 * a.alpha : 0;
-  const cx<R>* __restrict__ pw = a.twPost + (int64_t)k1 * L + t;
-  const cx<R>* __restrict__ q = a.twQ + (int64_t)j * L + t;
-  cx<R> w[EPT], wq[EPT];
-  if constexpr (EARLY) {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) w[e] = pw[TL * e];
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) wq[e] = q[TL * e];
-  }
 #pragma unroll
   for (int u = 0; u < EPT; ++u) ex[(kb + u * TL) * SR + rr] = g[u];
   __syncthreads();
   cx<R> v[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) v[e] = cconj(ex[(t + TL * e) * SR + r]);
-  if constexpr (EARLY) {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) w[e] = cmul(w[e], wq[e]);
-  }
   __syncthreads();  // the staging area becomes the FFT's exchange buffer
   const RowLayout<L> lay(r);
   line_fft<R, L, (TL <= 64)>(v, t, ex, lay, a.twL);
   if (ok) {
     cx<R>* gr = G + sig * a.y_stride + (int64_t)m1 * L + t;
-    if constexpr (!EARLY) {
-      // every twiddle load before the first store: loads and stores share
+    if constexpr (inv_twiddle_in_b<R>()) {
+      // the row's transform as it is: pass B applies the inter-pass twiddle
+      // as it reads the row back
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) gr[TL * e] = v[e];
+    } else {
+      // W_{alpha N}^{m1 n2} = W_N^{k1 n2} W_{alpha N}^{j n2}, m1 = alpha k1 + j;
+      // every twiddle load before the first store (loads and stores share
       // one in-order completion counter, so a load issued after a store
-      // would wait for that store too
+      // would wait for that store too)
+      const int k1 = m1 / a.alpha, j = m1 - k1 * a.alpha;
+      const cx<R>* __restrict__ pw = a.twPost + (int64_t)k1 * L + t;
+      const cx<R>* __restrict__ q = a.twQ + (int64_t)j * L + t;
+      cx<R> w[EPT];
 #pragma unroll
       for (int e = 0; e < EPT; ++e) w[e] = pw[TL * e];
 #pragma unroll
       for (int e = 0; e < EPT; ++e) w[e] = cmul(w[e], q[TL * e]);
-    }
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) gr[TL * e] = cmul(v[e], w[e]);
+      for (int e = 0; e < EPT; ++e) gr[TL * e] = cmul(v[e], w[e]);
+    }
   }
 }
 
 // Pass B: block = (signal, tile of C columns n2), every j.  Thread (c, t)
 // with c fastest owns column n2 = tile*C + c; for each j it reads the
-// elements k1 = t + TL e of G[alpha k1 + j][n2] (rows of C columns), runs the
+// elements k1 = t + TL e of G[alpha k1 + j][n2] (rows of C columns), times
+// the inter-pass twiddle W_{alpha N}^{m1 n2} = W_N^{k1 n2} W_{alpha N}^{j n2}
+// when this pass applies it (m1 = alpha k1 + j; the first factor is held for
+// every j, as in the forward pass 1, which forms the same product), runs the
 // length-N1 FFT and accumulates it times W_{alpha N1}^{j n1}; x[N2 n1 + n2]
 // is stored once, as rows of C columns.
 template <typename R, int L, int C>
@@ -180,14 +181,25 @@ __device__ __forceinline__ void body_passB(const cx<R>* __restrict__ G, cx<R>* _
   const cx<R>* gs = G + sig * a.y_stride;
   const unsigned in_off = (unsigned)(a.alpha * N2 * t + n2);  // lane part of (alpha k1 + j) N2 + n2
   const unsigned in_step = (unsigned)(a.alpha * N2 * TL);     // k1 -> k1 + TL
-  cx<R> acc[EPT];
+  const unsigned tw_off = (unsigned)(N2 * t + n2);  // lane part of N2 k1 + n2
+  const unsigned tw_step = (unsigned)(N2 * TL);
+  constexpr bool TWB = inv_twiddle_in_b<R>();
+  cx<R> acc[EPT], pw[EPT];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) acc[e] = {(R)0, (R)0};
+  for (int e = 0; e < EPT; ++e) {
+    acc[e] = {(R)0, (R)0};
+    if constexpr (TWB) pw[e] = colok ? (a.twPost + tw_step * e)[tw_off] : cx<R>{(R)0, (R)0};  // W_N^{k1 n2}
+  }
   for (int j = 0; j < a.alpha; ++j) {
     cx<R> v[EPT];
     const cx<R>* gj = gs + (int64_t)j * N2;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) v[e] = colok ? (gj + in_step * e)[in_off] : cx<R>{(R)0, (R)0};
+    if constexpr (TWB) {
+      const cx<R> q = colok ? a.twQ[j * N2 + n2] : cx<R>{(R)0, (R)0};  // W_{alpha N}^{j n2}
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[e] = cmul(v[e], cmul(pw[e], q));
+    }
     line_fft<R, L, false>(v, t, ex, lay, tws);
     if (j == 0) {
 #pragma unroll
