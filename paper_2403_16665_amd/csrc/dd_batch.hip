@@ -45,6 +45,7 @@ __device__ __forceinline__ DenseArgs<float> item_args(const BatchItem& it) {
   a.njg = it.njg;
   a.pre_lds = it.pre_lds;
   a.q_lds = it.q_lds;
+  a.post_split = it.post_split;
   a.scale = it.scale;
   a.twPre = it.twPre;
   a.twQ = it.twQ;

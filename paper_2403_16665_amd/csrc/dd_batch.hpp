@@ -103,6 +103,7 @@ struct BatchItem {
   int N1, N2, alpha, real;
   int lines1, ntile1, jgroup, njg, pre_lds;  // one pass: lines1 = thread groups sharing the signal
   int q_lds;              // pass 1: W_{alpha N}^{j n2} of a task's columns staged in LDS
+  int post_split;         // pass 1: W_N^{k1 n2} as the product of two table rows (DenseArgs)
   int ntile2;
   int p1_tasks;           // pass-1 tasks of the item
   int code1, code2;       // code paths: single or pass 1; pass 2 (-1: one pass)

@@ -196,6 +196,13 @@ inline void fill_item(BatchItem& it, const dd_desc& d, const ClassTables& ct, cx
     const size_t with_q =
         (size_t)pass1_lds_elems(sc.N1, C, pass1_pre_elems(it.pre_lds, d.alpha, sc.N1) + d.alpha * C) * 8;
     if ((size_t)d.alpha * C * 8 <= 4096 && with_q <= (size_t)BATCH_LDS_MAX) it.q_lds = 1;
+    // W_N^{k1 n2} from two rows of its table: the items of a batch belong to
+    // many classes whose tables do not stay in the L2, and a task then reads
+    // TL + EPT rows of its class's table instead of all N1 (that table is as
+    // large as the signal)
+    const int pre_q = pass1_pre_elems(it.pre_lds, d.alpha, sc.N1) + (it.q_lds ? d.alpha * C : 0);
+    it.post_split =
+        (size_t)pass1_lds_elems(sc.N1, C, pre_q + pass1_post_elems(sc.N1, C)) * 8 <= (size_t)BATCH_LDS_MAX ? 1 : 0;
     it.ntile2 = (d.alpha * sc.N1 + RB - 1) / RB;
     it.p1_tasks = it.ntile1 * it.njg;
     it.code1 = batch_code(BK_PASS1, sc.N1);
@@ -208,7 +215,10 @@ inline void fill_item(BatchItem& it, const dd_desc& d, const ClassTables& ct, cx
 inline size_t item_lds1(const BatchItem& it) {
   if (it.code2 < 0) return batch_single_lds(it.N1, it.alpha, it.lines1);
   const int C = batch_lines(it.N1);
-  return (size_t)pass1_lds_elems(it.N1, C, pass1_pre_elems(it.pre_lds, it.alpha, it.N1) + (it.q_lds ? it.alpha * C : 0)) * 8;
+  return (size_t)pass1_lds_elems(it.N1, C,
+                                 pass1_pre_elems(it.pre_lds, it.alpha, it.N1) + (it.q_lds ? it.alpha * C : 0) +
+                                     (it.post_split ? pass1_post_elems(it.N1, C) : 0)) *
+         8;
 }
 inline size_t item_lds2(const BatchItem& it) { return it.code2 < 0 ? 0 : lds_pass2(it.N2, batch_lines2(it.N2), 4); }
 

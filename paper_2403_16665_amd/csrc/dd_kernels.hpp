@@ -45,6 +45,9 @@ struct DenseArgs {
   int q_lds;          // pass 1: W_{alpha N}^{j n2} of the block's j range and columns staged in LDS
                       // (a global load inside the j loop would wait for the previous j's stores:
                       // loads and stores share one in-order counter)
+  int post_split;     // pass 1: W_N^{k1 n2} of element k1 = t + TL e formed as the product of the
+                      // table's rows t and TL e (the block's columns of rows TL e staged in LDS),
+                      // so that a block reads TL + EPT rows of the table instead of N1
   int hrows;          // 0: every row m1 of the scratch; real input: floor(alpha N1 / 2) + 1, the rows
                       // m1 <= alpha N1 / 2 that pass 1 stores and pass 2 transforms (the others are
                       // conjugate mirrors, X_{alpha N - m} = conj(X_m))
@@ -134,6 +137,9 @@ constexpr int line_threads(int L) { return L / make_line_plan(L).EPT; }
 constexpr int pass1_pre_elems(int mode, int jg, int L) {
   return mode == 1 ? jg * L : mode == 2 ? jg * (line_threads(L) + L / line_threads(L)) : 0;
 }
+// LDS elements of pass 1's staged rows TL e of the [k1][n2] table for C
+// columns (post_split), EPT elements per thread.
+constexpr int pass1_post_elems(int L, int C) { return (L / line_threads(L)) * C; }
 // Threads per line of the one-pass kernels (their plan: single_narrow).
 constexpr int single_line_threads(int L) { return L / make_line_plan(L, single_narrow(L)).EPT; }
 
@@ -363,6 +369,14 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
     }
   }
 
+  cx<R>* ps = qs + (a.q_lds ? (j1 - j0) * C : 0);  // [e][c] W_N^{TL e n2} (when a.post_split)
+  if (a.post_split) {
+    for (int i = tid; i < EPT * C; i += NT) {
+      const int col = tile * C + i % C;
+      ps[i] = col < a.N2 ? a.twPost[(int64_t)TL * (i / C) * a.N2 + col] : cx<R>{(R)0, (R)0};
+    }
+  }
+
   const bool colok = n2 < N2;  // a tile wider than N2 has idle columns
   cx<R> xv[EPT], pw[EPT];
   const unsigned in_off = (unsigned)(N2 * t + n2);          // lane part of N2 n1 + n2
@@ -371,8 +385,12 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
   if (colok) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) xv[e] = x(sig * a.x_stride + (int64_t)in_step * e, in_off);
+    if (a.post_split) {
+      pw[0] = a.twPost[in_off];  // W_N^{t n2}; the other elements after the staging
+    } else {
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) pw[e] = (a.twPost + in_step * e)[in_off];  // W_N^{k1 n2}, k1 = t + TL e
+      for (int e = 0; e < EPT; ++e) pw[e] = (a.twPost + in_step * e)[in_off];  // W_N^{k1 n2}, k1 = t + TL e
+    }
   } else {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) xv[e] = pw[e] = {(R)0, (R)0};
@@ -380,6 +398,11 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
 #pragma unroll
   for (int e = 0; e < EPT; ++e) xv[e] = cscale(xv[e], a.scale);
   __syncthreads();
+  if (a.post_split && colok) {
+    // W_N^{(t + TL e) n2} = W_N^{t n2} W_N^{TL e n2}
+#pragma unroll
+    for (int e = EPT - 1; e >= 1; --e) pw[e] = cmul(pw[0], ps[e * C + c]);
+  }
   const int S = a.yrow;  // scratch row stride
   const unsigned out_off = (unsigned)(a.alpha * S * t + n2);  // lane part of (alpha k1 + j) S + n2
   const unsigned out_step = (unsigned)(a.alpha * S * TL);
