@@ -404,7 +404,7 @@ def run_serving(args, rates=None, counts=None, tuned=False):
     out = {"plain": [], "batched": []}
     servers = {}
     for mode, name in ((dd.DD_SERVE_PLAIN, "plain"), (dd.DD_SERVE_BATCHED, "batched")):
-        srv = dd.dense_dft_server_create(mode=mode, hbm_budget_bytes=budget)
+        srv = dd.dense_dft_server_create(mode=mode, hbm_budget_bytes=budget, spin_us=getattr(args, "spin_us", 0))
         for (N, a), c in sorted(set(zip(mix, codes))):
             dd.dense_dft_server_warm(srv, N, a, N * dt, c)
         stream_through(srv, rates[-1], min(count, 4000), 99)      # warm-up pass over the stream
@@ -447,7 +447,8 @@ def run_serving(args, rates=None, counts=None, tuned=False):
                                "float32 real / complex64 input 1:1",
                    "requests_per_rate": counts, "rates_req_s": rates,
                    "N_range": [min(n for n, _ in mix), max(n for n, _ in mix)], "alphas": [2, 3, 4, 8, 16],
-                   "hbm_budget_bytes": budget},
+                   "hbm_budget_bytes": budget,
+                   "scheduler_spin_us": getattr(args, "spin_us", 0) or "library default (1000)"},
         "serving": out,
         "tuning": tuning,
         "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
@@ -694,6 +695,9 @@ def main():
     ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000,100000,200000,400000,800000",
                     help="serving: Poisson arrival rates (requests/s)")
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests per rate")
+    ap.add_argument("--spin-us", type=int, default=0, metavar="US",
+                    help="serving: how long the scheduler polls for requests when idle before it sleeps "
+                         "(0: the library's default, -1: sleeps at once)")
     ap.add_argument("--tune-db", default="", metavar="PATH",
                     help="default, real-input, inverse and uneven workloads: load the tuning table "
                          "from PATH if it exists, else tune and save it there (profiling runs then "

@@ -401,7 +401,8 @@ dd_status dense_dft_exec_many(const dd_desc *descs, int32_t count,
  * device's occupancy; a batch replays the smallest that covers its tasks;
  * the descriptor table is re-read from pinned host memory at every replay,
  * so one graph serves batches of any mix).
- * A scheduler thread fills a slot whenever one is free.  While every queued
+ * A scheduler thread fills a slot whenever one is free (when idle it polls
+ * for new requests for spin_us before it sleeps).  While every queued
  * request can have a free slot of its own, the head takes a slot alone (at
  * light load requests run concurrently on separate slots, each at its solo
  * latency); once requests outnumber the free slots, batches form.  Requests above
@@ -447,6 +448,10 @@ typedef struct dd_server_cfg {
     void *hip_stream;         /* NULL: a stream per slot; else every slot runs on this one */
     int64_t batch_max_bins;   /* larger requests (alpha*N bins) run as plain executions, which
                                  fill the device alone; 0 -> 2^20; -1 -> no limit */
+    int32_t spin_us;          /* with nothing to do, the scheduler thread keeps polling for new
+                                 requests this long before it sleeps (a sleeping thread takes
+                                 time to wake: the first request after a pause pays it);
+                                 0 -> 1000; -1 -> sleeps at once; at most 10^6 */
 } dd_server_cfg;
 
 typedef struct dd_result {

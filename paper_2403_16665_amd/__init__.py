@@ -499,7 +499,8 @@ def dense_dft_exec_many(descs, stream=None) -> None:
 class dd_server_cfg(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("mode", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
                 ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("max_queue", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p), ("batch_max_bins", ctypes.c_int64)]
+                ("flags", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p), ("batch_max_bins", ctypes.c_int64),
+                ("spin_us", ctypes.c_int32)]
 
 
 class dd_result(ctypes.Structure):
@@ -561,9 +562,10 @@ class Server:
 
 def dense_dft_server_create(device: int = 0, mode: int = DD_SERVE_BATCHED, hbm_budget_bytes: int = 0,
                             max_inflight: int = 0, max_batch: int = 0, max_queue: int = 0,
-                            flags: int = DD_TWIDDLE_FP64, hip_stream=None, batch_max_bins: int = 0) -> Server:
+                            flags: int = DD_TWIDDLE_FP64, hip_stream=None, batch_max_bins: int = 0,
+                            spin_us: int = 0) -> Server:
     cfg = dd_server_cfg(int(device), int(mode), int(hbm_budget_bytes), int(max_inflight), int(max_batch),
-                        int(max_queue), int(flags), hip_stream, int(batch_max_bins))
+                        int(max_queue), int(flags), hip_stream, int(batch_max_bins), int(spin_us))
     h = _vp()
     _check(_lib.dense_dft_server_create(ctypes.byref(cfg), ctypes.byref(h)), "dense_dft_server_create")
     return Server(h, cfg)

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdint>
@@ -90,6 +91,9 @@ struct dd_server {
   std::thread worker;
   std::mutex mu;  // queue, tickets, budget, pool ranges, slots' request lists, stats
   std::condition_variable cv_work, cv_done;
+  // bumped (under mu) with every notification of cv_work, so that the
+  // scheduler can poll for work without the lock
+  std::atomic<uint64_t> wake_gen{0};
   std::deque<Req*> pending;
   std::unordered_map<uint64_t, Req*> reqs;
   uint64_t next_ticket = 1;
@@ -290,6 +294,15 @@ void worker_main(dd_server* s) {
       lk.unlock();
       std::this_thread::yield();
       lk.lock();
+    } else if (s->cfg.spin_us > 0 && !s->paused && !s->stop) {
+      // idle: poll for a new request for spin_us, then sleep
+      const uint64_t seen = s->wake_gen.load(std::memory_order_relaxed);
+      lk.unlock();
+      const uint64_t until = clock_ns() + (uint64_t)s->cfg.spin_us * 1000u;
+      while (s->wake_gen.load(std::memory_order_acquire) == seen && clock_ns() < until) {
+      }
+      lk.lock();
+      if (s->wake_gen.load(std::memory_order_relaxed) == seen) s->cv_work.wait(lk);
     } else {
       s->cv_work.wait(lk);
     }
@@ -394,6 +407,8 @@ dd_status dense_dft_server_create(const dd_server_cfg* cfg, dd_server_t* out) {
     return DD_ERR_INVALID;
   if (c.flags & ~(uint32_t)(DD_TWIDDLE_FP32 | DD_SERVE_DETERMINISTIC)) return DD_ERR_INVALID;
   if (c.batch_max_bins < -1) return DD_ERR_INVALID;
+  if (c.spin_us < -1 || c.spin_us > 1000000) return DD_ERR_INVALID;
+  if (c.spin_us == 0) c.spin_us = 1000;
   if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = (size_t)8 << 30;
   if (c.max_inflight == 0) c.max_inflight = 8;
   if (c.max_batch == 0) c.max_batch = 256;
@@ -498,6 +513,7 @@ dd_status dense_dft_submit_at(dd_server_t s, const dd_desc* req, uint64_t t_arri
     }
     r->ticket = s->next_ticket++;
     s->pending.push_back(r);
+    s->wake_gen.fetch_add(1, std::memory_order_release);
     s->reqs.emplace(r->ticket, r);
     s->stats.submitted++;
     *ticket = r->ticket;
@@ -563,6 +579,7 @@ dd_status dense_dft_server_pause(dd_server_t s, int32_t paused) {
   {
     std::lock_guard<std::mutex> g(s->mu);
     s->paused = paused != 0;
+    s->wake_gen.fetch_add(1, std::memory_order_release);
   }
   s->cv_work.notify_one();
   return DD_OK;
@@ -585,6 +602,7 @@ dd_status dense_dft_server_destroy(dd_server_t s) {
     std::lock_guard<std::mutex> g(s->mu);
     s->stop = true;
     s->paused = false;
+    s->wake_gen.fetch_add(1, std::memory_order_release);
   }
   s->cv_work.notify_one();
   if (s->worker.joinable()) s->worker.join();

@@ -30,7 +30,8 @@ def test_admission_policy(tmp_path):
 
 @pytest.mark.parametrize("field,value", [
     ("mode", 5), ("max_inflight", -1), ("max_inflight", 65), ("max_batch", -2), ("max_batch", 4097),
-    ("max_queue", -1), ("flags", 4), ("flags", 0x200), ("batch_max_bins", -2),
+    ("max_queue", -1), ("flags", 4), ("flags", 0x200), ("batch_max_bins", -2), ("spin_us", -2),
+    ("spin_us", 1000001),
 ])
 def test_server_create_rejects_bad_config(field, value):
     import paper_2403_16665_amd as dd
