@@ -131,11 +131,14 @@ def test_serve_default_routing_alone_and_in_mix(oracle_mod):
 
 
 def test_serve_plain_mode_matches_plain_exec():
+    """Plain mode, with a scheduler that sleeps as soon as it is idle
+    (spin_us = -1): every request is one plain execution, bit-identical to
+    the plain transform."""
     import torch
     import paper_2403_16665_amd as dd
     reqs = make_requests(32, 12)
     xs, Xs = device_buffers(reqs)
-    srv = dd.dense_dft_server_create(mode=dd.DD_SERVE_PLAIN, hbm_budget_bytes=1 << 30)
+    srv = dd.dense_dft_server_create(mode=dd.DD_SERVE_PLAIN, hbm_budget_bytes=1 << 30, spin_us=-1)
     res = serve_all(srv, reqs, xs, Xs)
     assert all(r["batch_requests"] == 1 for r in res)
     st = dd.dense_dft_server_stats(srv)
