@@ -18,13 +18,16 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _run_pair(oracle_mod, N, alpha, batch, seed):
+def _run_pair(oracle_mod, N, alpha, batch, seed, sched=None):
     import torch
     import paper_2403_16665_amd as dd
     T = N * 1e-3
     x = np.stack([siggen.tones_complex(g, N, 1e-3) for g in siggen.rngs(seed, batch)])
     xd = torch.from_numpy(x).cuda()
-    plan = dd.dense_dft_plan(N, alpha, T, batch, dd.DD_C64)
+    if sched is None:
+        plan = dd.dense_dft_plan(N, alpha, T, batch, dd.DD_C64)
+    else:
+        plan = dd.dense_dft_plan_sched(N, alpha, T, batch, dd.DD_C64, dd.make_sched(**sched))
     Xa = torch.zeros(batch, alpha * N, dtype=torch.complex64, device="cuda")
     Xb = torch.full_like(Xa, float("nan"))
     dd.dense_dft_exec(plan, xd, Xa)
@@ -50,6 +53,17 @@ def test_static_scratch_matches_exec_twice(oracle_mod):
     # call's contents, which the second call must not depend on)
     p2 = _run_pair(oracle_mod, 16384, 4, 3, 42)
     assert dd.dense_dft_plan_info(p2)[0] == 2
+
+
+def test_static_scratch_padded_rows(oracle_mod):
+    """A schedule whose scratch rows are padded (2^18 x alpha 16 at 512 x 512:
+    row groups of 64 KiB, 36 MiB of scratch per signal instead of 32): the
+    static array holds one signal per chunk."""
+    import paper_2403_16665_amd as dd
+    N, alpha = 1 << 18, 16
+    p = _run_pair(oracle_mod, N, alpha, 2, 43, sched=dict(passes=2, N1=512, N2=512))
+    chunk = dd.dense_dft_plan_get_sched(p)["chunk"]
+    assert dd.dense_dft_workspace_size(p) == chunk * alpha * 512 * (512 + 64) * 8   # the rows are padded
 
 
 def test_static_scratch_refuses_oversized_signal():
