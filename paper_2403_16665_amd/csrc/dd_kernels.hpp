@@ -320,6 +320,26 @@ __device__ __forceinline__ void body_single_groups(const InAcc& x, cx<R>* __rest
 // precision and for lines of 5 * 2^a (20 elements per thread) that costs
 // occupancy or spills, so there the transform of j is reversed through LDS
 // and twiddled for the rows of alpha - j.
+// Copies n table entries into LDS with nt threads, U entries per thread per
+// round: a round issues all its loads before the first LDS write waits for
+// them (loads complete in order, so one wait covers the round).
+template <typename R, int U, class Get>
+__device__ __forceinline__ void stage_to_lds(cx<R>* dst, int n, int tid, int nt, Get get) {
+  for (int i0 = tid; i0 < n; i0 += U * nt) {
+    cx<R> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * nt;
+      v[u] = i < n ? get(i) : cx<R>{(R)0, (R)0};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * nt;
+      if (i < n) dst[i] = v[u];
+    }
+  }
+}
+
 template <typename R, class InAcc, int L, int C, bool HALF = false>
 __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y, const DenseArgs<R>& a,
                                            int64_t bid, unsigned char* smem, int tid) {
@@ -342,59 +362,67 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
   const int j0 = jg * a.jgroup;
   const int j1 = min(a.alpha, j0 + a.jgroup);
 
+  // the block's column.  Long columns (many loads per thread, from HBM) are
+  // issued before the tables below, so that their latency overlaps the
+  // tables' (2^22 x alpha 16, pass 1 at N1 = 2048 197 -> 189 us); short ones
+  // after (at N1 = 128 first cost 39.5 against 38.8 us per chunk).
+  constexpr bool COL_FIRST = L >= 1024;
+  const bool colok = n2 < N2;  // a tile wider than N2 has idle columns
+  cx<R> xv[EPT], pw[EPT];
+  const unsigned in_off = (unsigned)(N2 * t + n2);          // lane part of N2 n1 + n2
+  const unsigned in_step = (unsigned)(N2 * TL);             // n1 -> n1 + TL
+  auto load_column = [&]() {
+    if (colok) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) xv[e] = x(sig * a.x_stride + (int64_t)in_step * e, in_off);
+      if (a.post_split) {
+        pw[0] = a.twPost[in_off];  // W_N^{t n2}; the other elements after the staging
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) pw[e] = (a.twPost + in_step * e)[in_off];  // W_N^{k1 n2}, k1 = t + TL e
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) xv[e] = pw[e] = {(R)0, (R)0};
+    }
+  };
+  if constexpr (COL_FIRST) load_column();
+
   // twiddle tables of this block into LDS (read every j; from L2 their latency
   // sits on the critical path of each iteration, and a global load inside
   // the j loop waits for the previous j's stores: loads and stores share one
-  // in-order completion counter)
-  for (int i = tid; i < TWN; i += NT) tws[i] = a.twL[i];
+  // in-order completion counter).  Each copy gathers several entries per
+  // thread before it writes any, so that one wait covers their loads.
+  stage_to_lds<R, 4>(tws, TWN, tid, NT, [&](int i) { return a.twL[i]; });
   int pre_n = 0;
   if (a.pre_lds == 1) {
     // the block's rows of W_{alpha N1}^{j n1}, whole
     pre_n = (j1 - j0) * L;
-    for (int i = tid; i < pre_n; i += NT) pre[i] = a.twPre[j0 * L + i];
+    stage_to_lds<R, 4>(pre, pre_n, tid, NT, [&](int i) { return a.twPre[j0 * L + i]; });
   } else if (a.pre_lds == 2) {
     // columns too long to stage whole: the entries n1 = t ([j - j0][t]) and
     // n1 = TL e ([j - j0][e]) of the same rows, whose product is the factor
     const int na = (j1 - j0) * TL, nb = (j1 - j0) * EPT;
     pre_n = na + nb;
-    for (int i = tid; i < na; i += NT) pre[i] = a.twPre[(j0 + i / TL) * L + i % TL];
-    for (int i = tid; i < nb; i += NT) pre[na + i] = a.twPre[(j0 + i / EPT) * L + TL * (i % EPT)];
+    stage_to_lds<R, 4>(pre, pre_n, tid, NT, [&](int i) {
+      return i < na ? a.twPre[(j0 + i / TL) * L + i % TL] : a.twPre[(j0 + (i - na) / EPT) * L + TL * ((i - na) % EPT)];
+    });
   }
   cx<R>* qs = pre + pre_n;  // [j - j0][c] W_{alpha N}^{j n2} (when a.q_lds)
-  if (a.q_lds) {
-    const int n = (j1 - j0) * C;
-    for (int i = tid; i < n; i += NT) {
+  const int nq = a.q_lds ? (j1 - j0) * C : 0;
+  cx<R>* ps = qs + nq;      // [e][c] W_N^{TL e n2} (when a.post_split)
+  const int np = a.post_split ? EPT * C : 0;
+  // both in one copy: entries i < nq of qs, then the np of ps
+  stage_to_lds<R, 4>(qs, nq + np, tid, NT, [&](int i) {
+    if (i < nq) {
       const int col = tile * C + i % C;
-      qs[i] = col < a.N2 ? a.twQ[(j0 + i / C) * a.N2 + col] : cx<R>{(R)0, (R)0};
+      return col < a.N2 ? a.twQ[(j0 + i / C) * a.N2 + col] : cx<R>{(R)0, (R)0};
     }
-  }
+    const int k = i - nq, col = tile * C + k % C;
+    return col < a.N2 ? a.twPost[(int64_t)TL * (k / C) * a.N2 + col] : cx<R>{(R)0, (R)0};
+  });
 
-  cx<R>* ps = qs + (a.q_lds ? (j1 - j0) * C : 0);  // [e][c] W_N^{TL e n2} (when a.post_split)
-  if (a.post_split) {
-    for (int i = tid; i < EPT * C; i += NT) {
-      const int col = tile * C + i % C;
-      ps[i] = col < a.N2 ? a.twPost[(int64_t)TL * (i / C) * a.N2 + col] : cx<R>{(R)0, (R)0};
-    }
-  }
-
-  const bool colok = n2 < N2;  // a tile wider than N2 has idle columns
-  cx<R> xv[EPT], pw[EPT];
-  const unsigned in_off = (unsigned)(N2 * t + n2);          // lane part of N2 n1 + n2
-  const unsigned in_step = (unsigned)(N2 * TL);             // n1 -> n1 + TL
-  // every load of the column in flight at once, then one wait
-  if (colok) {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) xv[e] = x(sig * a.x_stride + (int64_t)in_step * e, in_off);
-    if (a.post_split) {
-      pw[0] = a.twPost[in_off];  // W_N^{t n2}; the other elements after the staging
-    } else {
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) pw[e] = (a.twPost + in_step * e)[in_off];  // W_N^{k1 n2}, k1 = t + TL e
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) xv[e] = pw[e] = {(R)0, (R)0};
-  }
+  if constexpr (!COL_FIRST) load_column();
 #pragma unroll
   for (int e = 0; e < EPT; ++e) xv[e] = cscale(xv[e], a.scale);
   __syncthreads();
