@@ -83,7 +83,7 @@ __device__ __forceinline__ void run_pass2(const BatchItem* __restrict__ items, i
   a.lines = batch_lines2(L);
   a.ntile = it.ntile2;
   a.twL = it.twL2;
-  body_pass2<float, L, batch_lines2(L)>(it.Y, it.X, a, sub, smem, tid);
+  body_pass2<float, L, batch_lines2(L), batch_lines2(L), true>(it.Y, it.X, a, sub, smem, tid);
 }
 
 // Persistent queue over the tasks of one launch (WHICH = 0: single-pass and

@@ -220,12 +220,16 @@ inline size_t item_lds1(const BatchItem& it) {
                                      (it.post_split ? pass1_post_elems(it.N1, C) : 0)) *
          8;
 }
-inline size_t item_lds2(const BatchItem& it) { return it.code2 < 0 ? 0 : lds_pass2(it.N2, batch_lines2(it.N2), 4); }
+// (pass-2 tasks stage their stage twiddles after the row buffers)
+inline size_t batch_lds2(int L) {
+  return lds_pass2(L, batch_lines2(L), 4) + (size_t)pass2_tw_elems(L, batch_lines2(L), 0, 8) * 8;
+}
+inline size_t item_lds2(const BatchItem& it) { return it.code2 < 0 ? 0 : batch_lds2(it.N2); }
 
 // Largest pass-2 LDS of any compiled pass-2 length (a server's fixed launch).
 inline size_t batch_lds2_max() {
   size_t m = 0;
-#define DD_L2(LL) m = std::max(m, lds_pass2(LL, batch_lines2(LL), 4));
+#define DD_L2(LL) m = std::max(m, batch_lds2(LL));
   DD_BATCH_P2(DD_L2)
 #undef DD_L2
   return m;

@@ -125,6 +125,12 @@ __host__ __device__ constexpr int pass2_lds_elems(int L, int RB, int rows = 0) {
   return (rows ? rows : RB) * (L + L / 16 + 1) > L * (RB + 1) ? (rows ? rows : RB) * (L + L / 16 + 1)
                                                              : L * (RB + 1);
 }
+// Stage twiddles of a pass-2 task staged in LDS after its row buffers (the
+// batch kernel's pass-2 tasks), when both fit a CU's LDS: entries, 0 if not.
+__host__ __device__ constexpr int pass2_tw_elems(int L, int RB, int rows, int cx_bytes) {
+  return (pass2_lds_elems(L, RB, rows) + line_tw_size(make_line_plan(L))) * cx_bytes <= 160 * 1024
+             ? line_tw_size(make_line_plan(L)) : 0;
+}
 
 // LDS of one block of a pass kernel may take all of a CU's 160 KiB: the wider
 // the tile, the longer the contiguous runs of its scattered stores.
@@ -563,7 +569,11 @@ __device__ __forceinline__ void body_pass1(const InAcc& x, cx<R>* __restrict__ Y
 // conjugate mirrors, which fill rows alpha N1 - H .. alpha N1 - 1 exactly once.
 // With ROWS = RB + 1 a block also transforms the first row of the next block,
 // so that its mirrored rows, (block*RB, block*RB + RB], land on whole runs.
-template <typename R, int L, int RB, int ROWS = RB>
+// TW_LDS: the stage twiddles are staged in LDS beside the row loads (the
+// batch kernel's tasks, which are bound by their latency: the uneven batch
+// 1.316 -> 1.282 ms); the plain kernel, bound by memory, reads them from the
+// L2 (staged, its pass 2 of 256 x 65536 took 62.5 instead of 59.7 us).
+template <typename R, int L, int RB, int ROWS = RB, bool TW_LDS = false>
 __device__ __forceinline__ void body_pass2(const cx<R>* __restrict__ Y, cx<R>* __restrict__ X,
                                            const DenseArgs<R>& a, int64_t bid, unsigned char* smem, int tid) {
   static_assert(ROWS == RB || ROWS == RB + 1, "a block transforms RB or RB + 1 rows");
@@ -585,7 +595,15 @@ __device__ __forceinline__ void body_pass2(const cx<R>* __restrict__ Y, cx<R>* _
 #pragma unroll
   for (int e = 0; e < EPT; ++e) v[e] = ok ? (ys + TL * e)[row_off] : cx<R>{(R)0, (R)0};
   const RowLayout<L> lay(r);
-  line_fft<R, L, (TL <= 64)>(v, t, ex, lay, a.twL);
+  constexpr int TWS = TW_LDS ? pass2_tw_elems(L, RB, ROWS, (int)sizeof(cx<R>)) : 0;
+  if constexpr (TWS > 0) {
+    cx<R>* tws = ex + pass2_lds_elems(L, RB, ROWS);
+    stage_to_lds<R, 4>(tws, TWS, tid, ROWS * TL, [&](int i) { return a.twL[i]; });
+    __syncthreads();
+    line_fft<R, L, (TL <= 64)>(v, t, ex, lay, tws);
+  } else {
+    line_fft<R, L, (TL <= 64)>(v, t, ex, lay, a.twL);
+  }
   __syncthreads();
   constexpr int SR = RB + 1;  // staging row stride (odd, spreads banks)
 #pragma unroll
