@@ -47,9 +47,9 @@ __device__ __forceinline__ DenseArgs<float> item_args(const BatchItem& it) {
   a.q_lds = it.q_lds;
   a.post_split = it.post_split;
   a.scale = it.scale;
-  a.twPre = it.twPre;
-  a.twQ = it.twQ;
-  a.twPost = it.twPost;
+  a.twPre = as_global(it.twPre);
+  a.twQ = as_global(it.twQ);
+  a.twPost = as_global(it.twPost);
   return a;
 }
 
@@ -59,8 +59,8 @@ __device__ __forceinline__ void run_single(const BatchItem* __restrict__ items, 
   const BatchItem& it = items[item];
   DenseArgs<float> a = item_args(it);
   a.lines = 1;
-  a.twL = it.twL1;
-  body_single_groups<float, AnyIn<float>, L>(AnyIn<float>{it.x, it.real}, it.X, a, sub, it.lines1, BATCH_THREADS,
+  a.twL = as_global(it.twL1);
+  body_single_groups<float, AnyIn<float>, L>(AnyIn<float>{as_global(it.x), it.real}, as_global(it.X), a, sub, it.lines1, BATCH_THREADS,
                                              smem, tid);
 }
 
@@ -71,8 +71,9 @@ __device__ __forceinline__ void run_pass1(const BatchItem* __restrict__ items, i
   DenseArgs<float> a = item_args(it);
   a.lines = batch_lines(L);
   a.ntile = it.ntile1;
-  a.twL = it.twL1;
-  body_pass1<float, AnyIn<float>, L, batch_lines(L)>(AnyIn<float>{it.x, it.real}, it.Y, a, sub, smem, tid);
+  a.twL = as_global(it.twL1);
+  body_pass1<float, AnyIn<float>, L, batch_lines(L)>(AnyIn<float>{as_global(it.x), it.real}, as_global(it.Y), a,
+                                                     sub, smem, tid);
 }
 
 template <int L>
@@ -82,8 +83,9 @@ __device__ __forceinline__ void run_pass2(const BatchItem* __restrict__ items, i
   DenseArgs<float> a = item_args(it);
   a.lines = batch_lines2(L);
   a.ntile = it.ntile2;
-  a.twL = it.twL2;
-  body_pass2<float, L, batch_lines2(L), batch_lines2(L), true>(it.Y, it.X, a, sub, smem, tid);
+  a.twL = as_global(it.twL2);
+  body_pass2<float, L, batch_lines2(L), batch_lines2(L), true>(as_global(it.Y), as_global(it.X), a, sub, smem,
+                                                                tid);
 }
 
 // Persistent queue over the tasks of one launch (WHICH = 0: single-pass and

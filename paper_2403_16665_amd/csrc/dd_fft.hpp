@@ -34,6 +34,16 @@ template <typename R>
 __device__ __forceinline__ cx<R> cscale(cx<R> a, R s) { return {a.re * s, a.im * s}; }
 template <typename R>
 __device__ __forceinline__ cx<R> cconj(cx<R> a) { return {a.re, -a.im}; }
+// A read through an LDS-qualified pointer.  Where either an LDS value or some
+// other value is chosen (a global table entry, or the thread's own register
+// array), the compiler would otherwise load through a pointer selected at run
+// time: a flat load, and a register array forced into private memory.
+template <typename R>
+__device__ __forceinline__ cx<R> lds_read(const cx<R>* p) {
+  const __attribute__((address_space(3))) R* q = (const __attribute__((address_space(3))) R*)p;
+  return {q[0], q[1]};
+}
+
 // -i * a
 template <typename R>
 __device__ __forceinline__ cx<R> cmul_negi(cx<R> a) { return {a.im, -a.re}; }
@@ -298,7 +308,8 @@ __device__ __forceinline__ void line_stage(cx<R>* v, int t, cx<R>* lds, const La
     for (int i = 0; i < NB; ++i) {
       const int b = t + TL * i;
 #pragma unroll
-      for (int s = 0; s < RAD; ++s) v[i + s * NB] = act ? lds[lay(b + s * (L / RAD))] : v[i + s * NB];
+      for (int s = 0; s < RAD; ++s)
+        if (act) v[i + s * NB] = lds_read(lds + lay(b + s * (L / RAD)));
     }
     const cx<R>* __restrict__ tws = twL + line_tw_offset(P, ST);
 #pragma unroll

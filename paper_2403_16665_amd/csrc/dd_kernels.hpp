@@ -58,12 +58,20 @@ struct DenseArgs {
   const cx<R>* twPost;// W_N^{k1 n2}, laid out [k1][n2]
 };
 
-// A read through an LDS-qualified pointer: keeps the compiler from merging it
-// with a global read of the other branch into one flat load.
-template <typename R>
-__device__ __forceinline__ cx<R> lds_read(const cx<R>* p) {
-  const __attribute__((address_space(3))) R* q = (const __attribute__((address_space(3))) R*)p;
-  return {q[0], q[1]};
+// A pointer into global memory, so marked for the compiler.  A pointer a kernel
+// reads from a descriptor in memory (not a kernel argument) is generic to it,
+// and generic accesses compile to flat loads and stores, which count on the LDS
+// counter as well as the memory counter: the LDS wait before every exchange
+// barrier then also waits for all stores still in flight.  The pointer passes
+// through the global address space behind an empty asm (a plain cast pair, or
+// an assumption on the address, is folded away before the compiler infers
+// address spaces), so every access derived from it is a global one.  The
+// pointers it is used on are uniform: the asm keeps them in scalar registers.
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+  __attribute__((address_space(1))) T* g;
+  asm("" : "=s"(g) : "0"((__attribute__((address_space(1))) T*)p));
+  return (T*)g;
 }
 
 // Store of a final output bin, marked non-temporal: the spectrum is not read
