@@ -215,7 +215,9 @@ dd_status dense_dft_plan_info(dd_plan_t plan, int32_t *passes, int64_t *N1,
 /* ---- Schedules and the tuner ----
  *
  * How a plan runs the transform.  One pass: each block holds the whole
- * alpha*N spectrum of `lines` signals in LDS.  Two passes, N = N1*N2 (the
+ * alpha*N spectrum of `lines` signals in LDS, and `jgroup` thread groups
+ * share each signal, group g computing the pre-twiddled FFTs of j = g,
+ * g + jgroup, ... at once with the others.  Two passes, N = N1*N2 (the
  * four-step split of the length-N FFTs of Section 3): pass 1 computes, for
  * every column n2, the alpha-dense DFT of length N1 (this library's
  * transform at size N1) times the inter-pass twiddles into a scratch of
@@ -223,9 +225,11 @@ dd_status dense_dft_plan_info(dd_plan_t plan, int32_t *passes, int64_t *N1,
  * the bins in natural order.  Zero fields take the planner's rule. */
 typedef struct dd_sched {
     int32_t passes;   /* 1 or 2 */
-    int32_t lines;    /* one pass: signals per block (0: as many as fit) */
+    int32_t lines;    /* one pass: signals per block (0: rule) */
     int64_t N1, N2;   /* two passes: N = N1*N2 (one pass: N1 = N, N2 = 1) */
-    int32_t jgroup;   /* two passes: values of j per pass-1 block, 1..alpha (0: rule) */
+    int32_t jgroup;   /* two passes: values of j per pass-1 block, 1..alpha;
+                         one pass: thread groups sharing a signal, each taking
+                         its own values of j, 1..alpha (0: rule) */
     int32_t reserved; /* 0 */
     int64_t chunk;    /* two passes: signals per pass pair (0: 128 MiB of scratch) */
 } dd_sched;
@@ -242,7 +246,10 @@ dd_status dense_dft_plan_get_sched(dd_plan_t plan, dd_sched *out);
 
 /* The schedules dense_dft_tune measures for this problem class, the
  * planner's current choice first, every field resolved; up to cap are
- * written, *count receives their number.  Host only (no device call).
+ * written, *count receives their number.  Host only: no device memory or
+ * launches (the planner's one-pass rule asks the runtime for the kernel's
+ * occupancy on the current device, and without a device uses an LDS
+ * model, so its first choice can differ between the two).
  * Errors: DD_ERR_INVALID, DD_ERR_UNSUPPORTED (no schedule for N). */
 dd_status dense_dft_sched_candidates(int64_t N, int32_t alpha, int64_t batch, dd_dtype dtype,
                                      dd_sched *out, int32_t cap, int32_t *count);

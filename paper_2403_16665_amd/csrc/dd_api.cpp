@@ -37,9 +37,12 @@ struct dd_plan {
   bool dbl = false;
   int in_bytes = 8, rbytes = 4;
   int passes = 1;
-  // single pass
-  int s_lines = 1, s_TL = 1;
-  size_t s_lds = 0;
+  // single pass: s_lines signals per block, s_groups thread groups per
+  // signal (each takes its own values of j); the inverse's one-pass kernel
+  // sums over j in each thread, so it runs one group per signal and
+  // s_inv_lines signals per block
+  int s_lines = 1, s_groups = 1, s_TL = 1, s_inv_lines = 1;
+  size_t s_lds = 0, s_inv_lds = 0;
   // two passes
   int p1_lines = 1, p1_TL = 1, p1_ntile = 1, p1_jgroup = 1, p1_njg = 1, p1_pre_lds = 0, p1_q_lds = 0;
   size_t p1_lds = 0;
@@ -152,6 +155,83 @@ bool factor_two_pass(int64_t N, int rbytes, int64_t* N1, int64_t* N2) {
 // One-pass blocks hold the spectrum of `lines` signals in LDS within this.
 constexpr size_t SINGLE_BUDGET = 150 * 1024;
 
+// One-pass block shapes.  A signal's jn transformed values of j are shared by
+// G thread groups in ceil(jn / G) rounds; the group counts worth running are
+// the fewest that finish in 1, 2, ... rounds, within the block (gl groups).
+// Signals per block: the most that fit beside them, then powers of two below.
+std::vector<int> single_group_options(int jn, int gl) {
+  std::vector<int> o;
+  for (int r = 1; r <= jn; ++r) {
+    const int G = (jn + r - 1) / r;
+    if (G <= gl && (o.empty() || o.back() != G)) o.push_back(G);
+  }
+  return o;
+}
+std::vector<int> single_line_options(int gl, int G) {
+  std::vector<int> o;
+  const int top = gl / G;
+  if (top >= 1) o.push_back(top);
+  int l = 1;
+  while (2 * l <= top) l *= 2;
+  for (; l >= 1; l /= 2)
+    if (l != top) o.push_back(l);
+  return o;
+}
+int single_jn(int alpha, bool real) { return real ? alpha / 2 + 1 : alpha; }
+
+// The built-in one-pass shape (a zero argument is chosen, a nonzero one
+// kept).  Score: the lanes a CU holds doing work -- resident blocks (from the
+// runtime's occupancy of the kernel, which counts registers, LDS and
+// wavefront slots; without a device, from LDS and 32 wavefront slots, at most
+// 16 blocks) times the block's threads, each wavefront counted at the share
+// of its lanes in use, times the share of group slots with a j to transform.
+// Among the shapes within 10% of the best score the smallest block wins
+// (measured: at equal resident lanes, more and smaller blocks wait less at
+// their barriers), then fewer rounds over j, then more signals per block.
+void single_shape(int L, int alpha, bool real, int rbytes, int64_t batch, int* lines_io, int* groups_io) {
+  const KGeom g = geom_single(L, rbytes);
+  const int jn = single_jn(alpha, real);
+  struct Shape {
+    int lines, groups, block, rounds;
+    double score;
+  };
+  std::vector<Shape> shapes;
+  double best = 0;
+  for (const int G : single_group_options(jn, g.lines)) {
+    if (*groups_io > 0 && G != *groups_io) continue;
+    for (const int l : single_line_options(g.lines, G)) {
+      if (*lines_io > 0 && l != *lines_io) continue;
+      if (l > 1 && l > batch) continue;
+      const size_t lds = lds_single(L, l, alpha, rbytes, G);
+      if (lds > SINGLE_BUDGET) continue;
+      const int block = l * G * g.TL;
+      const int waves = (block + 63) / 64;
+      int64_t blocks = rbytes == 4 ? single_occupancy(L, real, 0.0f, block, lds)
+                                   : single_occupancy(L, real, 0.0, block, lds);
+      if (blocks <= 0) {
+        blocks = (int64_t)(160 * 1024 / lds);
+        if (blocks > 32 / waves) blocks = 32 / waves;
+        if (blocks > 16) blocks = 16;
+      }
+      const int rounds = (jn + G - 1) / G;
+      double lanes = (double)blocks * block * block / (64.0 * waves);
+      if (lanes > 1024) lanes = 1024;
+      const double score = lanes * jn / ((double)rounds * G);
+      shapes.push_back({l, G, block, rounds, score});
+      if (score > best) best = score;
+    }
+  }
+  const Shape* pick = nullptr;
+  for (const Shape& c : shapes) {
+    if (c.score < 0.9 * best) continue;
+    if (!pick || c.block < pick->block || (c.block == pick->block && (c.rounds < pick->rounds ||
+                                                                      (c.rounds == pick->rounds && c.lines > pick->lines))))
+      pick = &c;
+  }
+  if (*lines_io <= 0) *lines_io = pick ? pick->lines : 1;
+  if (*groups_io <= 0) *groups_io = pick ? pick->groups : 1;
+}
+
 // Built-in schedule rules: one pass when the alpha*N spectrum of a signal
 // fits the LDS of one block, else the most balanced two-pass split; tile
 // choices left to configure().
@@ -181,21 +261,28 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
   if (sc.passes == 1) {
     if (N > 4096 || !len_supported((int)N)) return DD_ERR_UNSUPPORTED;
     const KGeom g = geom_single((int)N, p->rbytes);
-    const size_t per_line = lds_single((int)N, 1, alpha, p->rbytes);
-    if (per_line > SINGLE_BUDGET) return DD_ERR_UNSUPPORTED;
-    int lines = sc.lines;
-    if (lines <= 0) {
-      lines = g.lines;
-      while (lines > 1 && (size_t)lines * per_line > SINGLE_BUDGET) lines /= 2;
-    }
-    if (lines > g.lines || (size_t)lines * per_line > SINGLE_BUDGET) return DD_ERR_UNSUPPORTED;
+    if (lds_single((int)N, 1, alpha, p->rbytes) > SINGLE_BUDGET) return DD_ERR_UNSUPPORTED;
+    if (sc.lines < 0 || sc.jgroup < 0 || sc.jgroup > alpha) return DD_ERR_UNSUPPORTED;
+    const bool real = p->dtype == DD_F32 || p->dtype == DD_F64;
+    int lines = sc.lines, groups = sc.jgroup;
+    if (lines == 0 || groups == 0) single_shape((int)N, alpha, real, p->rbytes, batch, &lines, &groups);
+    if ((int64_t)lines * groups > g.lines || lds_single((int)N, lines, alpha, p->rbytes, groups) > SINGLE_BUDGET)
+      return DD_ERR_UNSUPPORTED;
     if (lines > batch) lines = (int)batch;
+    // the inverse: as many signals per block as the forward has groups in
+    // all, within the LDS budget
+    int il = lines * groups;
+    while (il > 1 && lds_single((int)N, il, alpha, p->rbytes) > SINGLE_BUDGET) il /= 2;
+    if (il > batch) il = (int)batch;
     p->passes = 1;
     p->N1 = N;
     p->N2 = 1;
     p->s_lines = lines;
+    p->s_groups = groups;
     p->s_TL = g.TL;
-    p->s_lds = lds_single((int)N, lines, alpha, p->rbytes);
+    p->s_lds = lds_single((int)N, lines, alpha, p->rbytes, groups);
+    p->s_inv_lines = il;
+    p->s_inv_lds = lds_single((int)N, il, alpha, p->rbytes);
     p->ws_bytes = 0;
     return DD_OK;
   }
@@ -311,7 +398,7 @@ dd_sched resolved(const dd_plan* p) {
   o.lines = p->passes == 1 ? p->s_lines : 0;
   o.N1 = p->N1;
   o.N2 = p->N2;
-  o.jgroup = p->passes == 2 ? p->p1_jgroup : 0;
+  o.jgroup = p->passes == 2 ? p->p1_jgroup : p->s_groups;
   o.chunk = p->passes == 2 ? p->chunk : 0;
   return o;
 }
@@ -491,15 +578,18 @@ dd_status dense_dft_sched_candidates(int64_t N, int32_t alpha, int64_t batch, dd
   };
   if (configure_auto(&p) == DD_OK) add(resolved(&p));
   if (N <= 4096 && len_supported((int)N)) {
-    for (int lines = geom_single((int)N, p.rbytes).lines; lines >= 1; lines /= 2) {
-      if (lines > batch) continue;
-      dd_sched sc{};
-      sc.passes = 1;
-      sc.lines = lines;
-      sc.N1 = N;
-      sc.N2 = 1;
-      add(sc);
-    }
+    const KGeom g = geom_single((int)N, p.rbytes);
+    for (const int groups : single_group_options(single_jn(alpha, dtype == DD_F32 || dtype == DD_F64), g.lines))
+      for (const int lines : single_line_options(g.lines, groups)) {
+        if (lines > batch) continue;
+        dd_sched sc{};
+        sc.passes = 1;
+        sc.lines = lines;
+        sc.jgroup = groups;
+        sc.N1 = N;
+        sc.N2 = 1;
+        add(sc);
+      }
   }
   for (int64_t n2 = 2; n2 <= 4096; n2 *= 2) {
     if (N % n2) continue;
@@ -563,10 +653,11 @@ dd_status exec_typed(dd_plan* p, const In* x, cx<R>* X, cx<R>* ws, hipStream_t s
     a.N2 = 1;
     a.alpha = p->alpha;
     a.lines = p->s_lines;
+    a.jgroup = p->s_groups;
     a.scale = scale;
     a.twL = static_cast<const cx<R>*>(p->twL1);
     a.twPre = static_cast<const cx<R>*>(p->twPre);
-    const int block = p->s_lines * p->s_TL;
+    const int block = p->s_lines * p->s_groups * p->s_TL;
     const int64_t per = max_launch_blocks(block) * p->s_lines;  // signals per launch
     for (int64_t b0 = 0; b0 < p->batch; b0 += per) {
       a.batch = p->batch - b0 < per ? p->batch - b0 : per;
@@ -636,15 +727,15 @@ dd_status exec_inverse_typed(dd_plan* p, const cx<R>* X, cx<R>* x, cx<R>* ws, hi
     a.N1 = (int)p->N;
     a.N2 = 1;
     a.alpha = p->alpha;
-    a.lines = p->s_lines;
+    a.lines = p->s_inv_lines;
     a.scale = scale;
     a.twL = static_cast<const cx<R>*>(p->twL1);
     a.twPre = static_cast<const cx<R>*>(p->twPre);
-    const int block = p->s_lines * p->s_TL;
-    const int64_t per = max_launch_blocks(block) * p->s_lines;  // signals per launch
+    const int block = p->s_inv_lines * p->s_TL;
+    const int64_t per = max_launch_blocks(block) * p->s_inv_lines;  // signals per launch
     for (int64_t b0 = 0; b0 < p->batch; b0 += per) {
       a.batch = p->batch - b0 < per ? p->batch - b0 : per;
-      LaunchCfg c{(a.batch + p->s_lines - 1) / p->s_lines, block, p->s_lds, s};
+      LaunchCfg c{(a.batch + p->s_inv_lines - 1) / p->s_inv_lines, block, p->s_inv_lds, s};
       const hipError_t e =
           timed_launch(p, 4, s, [&] { return launch_single_inv((int)p->N, c, X + b0 * M, x + b0 * p->N, a); });
       if (e != hipSuccess) return hip_status(e);

@@ -21,6 +21,28 @@ hipError_t launch_single_impl(int L, const LaunchCfg& c, const In* x, cx<R>* X, 
   }
 }
 
+// Blocks of the one-pass kernel resident per CU for a block size and LDS
+// size (registers, LDS and wavefront slots together); 0 if the runtime
+// cannot tell (no device).
+template <typename R, typename In>
+int single_occupancy_impl(int L, int block, size_t lds) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (L) {
+#define DD_CASE(LL)                                                                          \
+  case LL: {                                                                                 \
+    constexpr int B = Geom<LL, (int)sizeof(R)>::BLOCK_SINGLE;                                \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_single<R, In, LL, B>, block, lds); \
+    break;                                                                                   \
+  }
+    DD_ALL_LENGTHS(DD_CASE)
+#undef DD_CASE
+    default:
+      break;
+  }
+  return e == hipSuccess && n > 0 ? n : 0;
+}
+
 template <typename R, typename In>
 hipError_t launch_pass1_impl(int L, const LaunchCfg& c, const In* x, cx<R>* Y, const DenseArgs<R>& a) {
   switch (L) {

@@ -39,7 +39,8 @@ struct DenseArgs {
   int N1, N2, alpha;
   int lines;          // lines per block: signals (single), columns (pass 1), rows (pass 2)
   int ntile;          // column tiles (pass 1) or row blocks (pass 2) per signal
-  int jgroup, njg;    // j values per block and number of j groups (pass 1)
+  int jgroup, njg;    // pass 1: j values per block and number of j groups; one pass: thread groups
+                      // sharing a signal (jgroup; group g takes j = g, g + jgroup, ...)
   int pre_lds;        // pass 1: pre-twiddles of the block's j range staged in LDS: 1 whole rows,
                       // 2 the entries n1 < TL and n1 = TL e of each row (their product is the factor)
   int q_lds;          // pass 1: W_{alpha N}^{j n2} of the block's j range and columns staged in LDS
@@ -198,38 +199,50 @@ struct Geom {
 // dynamic LDS base, `tid` the thread's index in the block.
 // ---------------------------------------------------------------------------
 
-// Single pass: block = a.lines signals; thread t of line `line` owns samples
-// t + TL e.  LDS: exchange (RowLayout, a.lines lines) then the spectrum image.
-// Threads beyond a.lines * TL only take part in synchronisation.
+// Single pass: block = a.lines signals, each shared by a.jgroup groups of TL
+// threads; group g of a signal takes the values j = g, g + jgroup, ... and
+// thread t of a group owns samples t + TL e.  LDS: one exchange row per group
+// (RowLayout), then the lines' spectrum images.  The block first loads its
+// signals' samples into the head of their images (one coalesced read of each
+// sample, however many groups share the signal).  Threads beyond
+// a.lines * a.jgroup * TL only take part in synchronisation.
 template <typename R, class InAcc, int L>
 __device__ __forceinline__ void body_single(const InAcc& x, cx<R>* __restrict__ X, const DenseArgs<R>& a,
                                             int64_t bid, int nt, unsigned char* smem, int tid) {
   constexpr LinePlan P = make_line_plan(L, single_narrow(L));
   constexpr int EPT = P.EPT;
   constexpr int TL = L / EPT;
+  const int G = a.jgroup;
   cx<R>* ex = reinterpret_cast<cx<R>*>(smem);
-  cx<R>* img = ex + RowLayout<L>::elems(a.lines);
-  const int t = tid % TL, line = tid / TL;
-  const bool act = line < a.lines;
+  cx<R>* img = ex + RowLayout<L>::elems(a.lines * G);
+  const int t = tid % TL, gi = tid / TL, line = gi / G, g = gi % G;
+  const bool member = line < a.lines;
   const int64_t sig0 = bid * a.lines;
   const int64_t sig = sig0 + line;
-  const bool active = act && sig < a.batch;
+  const bool active = member && sig < a.batch;
   const int M1 = a.alpha * L;
-
+  const int64_t nl = min((int64_t)a.lines, a.batch - sig0);
+  for (int i = tid; i < nl * L; i += nt) {
+    const int sl = i / L, n = i - sl * L;
+    img[sl * M1 + n] = cscale(x((sig0 + sl) * a.x_stride, (unsigned)n), a.scale);
+  }
+  __syncthreads();
+  cx<R>* im = img + (int64_t)(member ? line : 0) * M1;
   cx<R> xv[EPT];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e)
-    xv[e] = active ? cscale(x(sig * a.x_stride, (unsigned)(t + TL * e)), a.scale) : cx<R>{(R)0, (R)0};
-  const RowLayout<L> lay(act ? line : 0);
-  cx<R>* im = img + (int64_t)line * M1;
+  for (int e = 0; e < EPT; ++e) xv[e] = active ? lds_read(im + t + TL * e) : cx<R>{(R)0, (R)0};
+  __syncthreads();  // every group holds its samples before any writes its spectrum over them
+  const RowLayout<L> lay(member ? gi : 0);
   // real samples: X_{alpha L - m} = conj(X_m), so with m = alpha k + j the
   // bins of alpha - j are conj(X_{alpha (L - 1 - k) + j}); only j <= alpha/2
   // are transformed, and each j in [1, alpha/2) also fills its mirror
   const bool herm = x.is_real();
   const int jmax = herm ? a.alpha / 2 : a.alpha - 1;
-  for (int j = 0; j <= jmax; ++j) {
+  for (int j0 = 0; j0 <= jmax; j0 += G) {  // uniform over the block
+    const int j = j0 + g;
+    const bool act = member && j <= jmax;
     cx<R> v[EPT];
-    if (j == 0) {
+    if (j == 0 || !act) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) v[e] = xv[e];
     } else {
@@ -248,7 +261,6 @@ __device__ __forceinline__ void body_single(const InAcc& x, cx<R>* __restrict__ 
     }
   }
   __syncthreads();
-  const int64_t nl = min((int64_t)a.lines, a.batch - sig0);
   const int64_t total = nl * M1;
   cx<R>* dst = X + sig0 * a.y_stride;  // y_stride == alpha * L
   for (int64_t i = tid; i < total; i += nt) store_out(dst + i, img[i]);

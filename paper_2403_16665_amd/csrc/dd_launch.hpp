@@ -58,6 +58,10 @@ KGeom geom_pass2(int L, int rbytes);  // forward pass 2 of complex input (lines_
 DD_DECL_LAUNCHERS(float)
 DD_DECL_LAUNCHERS(double)
 #undef DD_DECL_LAUNCHERS
+// Blocks of the one-pass kernel (real or complex input, arithmetic of the
+// tag's type) resident per CU at this block and LDS size; 0 if unknown.
+int single_occupancy(int L, bool real, float tag, int block, size_t lds);
+int single_occupancy(int L, bool real, double tag, int block, size_t lds);
 
 struct BatchItem;
 struct BatchMeta;
@@ -75,8 +79,9 @@ hipError_t launch_batch(const void* tab_host, void* tab_dev, int cap, unsigned* 
 int batch_max_blocks_per_cu(int which, size_t lds);
 
 // LDS bytes of each kernel for a given length and lines per block.
-inline size_t lds_single(int L, int lines, int alpha, int rbytes) {
-  return (size_t)lines * ((size_t)(L + L / 16 + 1) + (size_t)alpha * L) * 2 * rbytes;
+// One pass: `lines` signals per block, `groups` exchange rows per signal.
+inline size_t lds_single(int L, int lines, int alpha, int rbytes, int groups = 1) {
+  return (size_t)lines * ((size_t)groups * (L + L / 16 + 1) + (size_t)alpha * L) * 2 * rbytes;
 }
 inline size_t lds_pass1(int L, int lines, int rbytes, int pre_elems) {
   return (size_t)pass1_lds_elems(L, lines, pre_elems) * 2 * rbytes;

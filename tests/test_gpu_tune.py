@@ -42,7 +42,7 @@ def inputs(code, N, batch, seed):
 
 @pytest.mark.parametrize("N,alpha,batch,code", [
     (1024, 16, 1, 1), (4096, 4, 2, 0), (3 * 2 ** 15, 3, 2, 1), (1024, 4, 1, 2), (65536, 8, 3, 1),
-    (5 * 2 ** 12, 2, 2, 3)])
+    (5 * 2 ** 12, 2, 2, 3), (256, 8, 37, 1), (320, 3, 13, 0), (48, 5, 29, 1)])
 def test_every_plan_schedule_matches_oracle(dd, oracle_mod, N, alpha, batch, code):
     import torch
     x = inputs(code, N, batch, 11)
@@ -101,3 +101,27 @@ def test_tune_plan_and_reload(dd, tmp_path):
     assert dd.dense_dft_tune_entries() == (2, 1)
     plan = dd.dense_dft_plan(1024, 16, 1.024, 1, dd.DD_C64)
     assert dd.dense_dft_plan_get_sched(plan) == info["best"]
+
+
+@pytest.mark.parametrize("N,alpha,batch,code", [(256, 8, 37, 1), (384, 3, 13, 0), (1024, 4, 5, 3)])
+def test_every_one_pass_schedule_round_trips(dd, N, alpha, batch, code):
+    # the inverse runs one thread group per signal whatever the forward's
+    # groups; its signals per block follow the schedule
+    import torch
+    x = inputs(code, N, batch, 5)
+    xd = torch.from_numpy(x).cuda()
+    T = N * 1e-3
+    cands = [sc for sc in dd.dense_dft_sched_candidates(N, alpha, batch, code) if sc.passes == 1]
+    assert len(cands) >= 2
+    tol = 1e-12 if code in (dd.DD_F64, dd.DD_C128) else 1e-5
+    for sc in cands:
+        plan = dd.dense_dft_plan_sched(N, alpha, T, batch, code, sc)
+        X = dd.alpha_dft(xd, alpha, T, plan=plan)
+        back = torch.empty((batch, N), dtype=X.dtype, device="cuda")
+        dd.dense_dft_exec_inverse(plan, X, back)
+        torch.cuda.synchronize()
+        back = back.cpu().numpy()
+        for b in range(batch):
+            ref = x[b].astype(back.dtype)
+            r = np.linalg.norm(back[b] - ref) / np.linalg.norm(ref)
+            assert r <= tol, f"schedule {sc.as_dict()} signal {b}: round trip rel L2 {r:.3e}"

@@ -31,7 +31,8 @@ def test_candidates_are_valid_schedules(dd, N, alpha, batch, dtype):
         assert s.passes in (1, 2)
         assert s.N1 * s.N2 == N
         if s.passes == 1:
-            assert s.N2 == 1 and 1 <= s.lines <= batch
+            # lines signals per block, jgroup thread groups per signal
+            assert s.N2 == 1 and 1 <= s.lines <= batch and 1 <= s.jgroup <= alpha
         else:
             assert 1 <= s.jgroup <= alpha and 1 <= s.chunk <= batch and s.N2 & (s.N2 - 1) == 0
         keys.add((s.passes, s.lines, s.N1, s.N2, s.jgroup, s.chunk))
@@ -48,6 +49,24 @@ def test_plan_sched_refuses_bad_schedules(dd, sched):
     assert dd._lib.dense_dft_plan_sched(ctypes.byref(h), 65536, 8, 1.0, 4, dd.DD_C64, 0, ctypes.byref(sc)) == 2
     assert not h.value
     assert dd._lib.dense_dft_plan_sched(ctypes.byref(h), 65536, 8, 1.0, 4, dd.DD_C64, 0, None) == 1
+
+
+@pytest.mark.parametrize("lines,jgroup", [(1, 5), (4, 4), (2, 3), (-1, 1), (1, -2)])
+def test_plan_sched_refuses_bad_one_pass_shapes(dd, lines, jgroup):
+    # N = 1024 runs 64 threads per line, 4 lines per block: lines * jgroup <= 4, jgroup <= alpha
+    h = ctypes.c_void_p(3)
+    sc = dd.make_sched(passes=1, N1=1024, N2=1, lines=lines, jgroup=jgroup)
+    assert dd._lib.dense_dft_plan_sched(ctypes.byref(h), 1024, 4, 1.0, 8, dd.DD_C64, 0, ctypes.byref(sc)) == 2
+    assert not h.value
+
+
+def test_one_pass_rule_shares_signals_between_groups(dd):
+    # the planner's one-pass shape: every value of j of a signal in one round
+    # where the block holds them (complex input: alpha values; real: alpha/2 + 1)
+    for N, alpha, batch, dtype, groups in [(1024, 4, 1, dd.DD_F32, 3), (1024, 4, 64, dd.DD_C64, 4),
+                                           (256, 8, 4096, dd.DD_C64, 8), (64, 16, 100, dd.DD_C64, 16)]:
+        s = dd.dense_dft_sched_candidates(N, alpha, batch, dtype)[0]
+        assert (s.passes, s.jgroup) == (1, groups)
 
 
 def test_batch_candidates(dd):
