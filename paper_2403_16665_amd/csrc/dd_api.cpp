@@ -37,12 +37,10 @@ struct dd_plan {
   bool dbl = false;
   int in_bytes = 8, rbytes = 4;
   int passes = 1;
-  // single pass: s_lines signals per block, s_groups thread groups per
-  // signal (each takes its own values of j); the inverse's one-pass kernel
-  // sums over j in each thread, so it runs one group per signal and
-  // s_inv_lines signals per block
-  int s_lines = 1, s_groups = 1, s_TL = 1, s_inv_lines = 1;
-  size_t s_lds = 0, s_inv_lds = 0;
+  // single pass (forward and inverse): s_lines signals per block, s_groups
+  // thread groups per signal (each takes its own values of j)
+  int s_lines = 1, s_groups = 1, s_TL = 1;
+  size_t s_lds = 0;
   // two passes
   int p1_lines = 1, p1_TL = 1, p1_ntile = 1, p1_jgroup = 1, p1_njg = 1, p1_pre_lds = 0, p1_q_lds = 0;
   size_t p1_lds = 0;
@@ -269,11 +267,6 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
     if ((int64_t)lines * groups > g.lines || lds_single((int)N, lines, alpha, p->rbytes, groups) > SINGLE_BUDGET)
       return DD_ERR_UNSUPPORTED;
     if (lines > batch) lines = (int)batch;
-    // the inverse: as many signals per block as the forward has groups in
-    // all, within the LDS budget
-    int il = lines * groups;
-    while (il > 1 && lds_single((int)N, il, alpha, p->rbytes) > SINGLE_BUDGET) il /= 2;
-    if (il > batch) il = (int)batch;
     p->passes = 1;
     p->N1 = N;
     p->N2 = 1;
@@ -281,8 +274,6 @@ dd_status configure(dd_plan* p, const dd_sched& sc) {
     p->s_groups = groups;
     p->s_TL = g.TL;
     p->s_lds = lds_single((int)N, lines, alpha, p->rbytes, groups);
-    p->s_inv_lines = il;
-    p->s_inv_lds = lds_single((int)N, il, alpha, p->rbytes);
     p->ws_bytes = 0;
     return DD_OK;
   }
@@ -727,15 +718,16 @@ dd_status exec_inverse_typed(dd_plan* p, const cx<R>* X, cx<R>* x, cx<R>* ws, hi
     a.N1 = (int)p->N;
     a.N2 = 1;
     a.alpha = p->alpha;
-    a.lines = p->s_inv_lines;
+    a.lines = p->s_lines;
+    a.jgroup = p->s_groups;
     a.scale = scale;
     a.twL = static_cast<const cx<R>*>(p->twL1);
     a.twPre = static_cast<const cx<R>*>(p->twPre);
-    const int block = p->s_inv_lines * p->s_TL;
-    const int64_t per = max_launch_blocks(block) * p->s_inv_lines;  // signals per launch
+    const int block = p->s_lines * p->s_groups * p->s_TL;
+    const int64_t per = max_launch_blocks(block) * p->s_lines;  // signals per launch
     for (int64_t b0 = 0; b0 < p->batch; b0 += per) {
       a.batch = p->batch - b0 < per ? p->batch - b0 : per;
-      LaunchCfg c{(a.batch + p->s_inv_lines - 1) / p->s_inv_lines, block, p->s_inv_lds, s};
+      LaunchCfg c{(a.batch + p->s_lines - 1) / p->s_lines, block, p->s_lds, s};
       const hipError_t e =
           timed_launch(p, 4, s, [&] { return launch_single_inv((int)p->N, c, X + b0 * M, x + b0 * p->N, a); });
       if (e != hipSuccess) return hip_status(e);

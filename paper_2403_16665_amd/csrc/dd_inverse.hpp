@@ -25,9 +25,13 @@
 
 namespace dd {
 
-// One pass: block = `lines` signals.  Their alpha*L spectra are staged in LDS
-// with one contiguous load; for each j, thread t of a line gathers the
-// elements k = t + TL e of the subsequence X_{alpha k + j}.
+// One pass: block = a.lines signals, each shared by a.jgroup groups of TL
+// threads (group g takes j = g, g + jgroup, ...).  Their alpha*L spectra are
+// staged in LDS with one contiguous load; for each j, thread t of a group
+// gathers the elements k = t + TL e of the subsequence X_{alpha k + j}.  Each
+// group sums its values of j in registers; with several groups the partial
+// sums meet in the groups' exchange rows and the signal's first group adds
+// them in order of g.
 template <typename R, int L>
 __device__ __forceinline__ void body_single_inv(const cx<R>* __restrict__ X, cx<R>* __restrict__ x,
                                                 const DenseArgs<R>& a, int64_t bid, int nt, unsigned char* smem,
@@ -35,38 +39,59 @@ __device__ __forceinline__ void body_single_inv(const cx<R>* __restrict__ X, cx<
   constexpr LinePlan P = make_line_plan(L, single_narrow(L));
   constexpr int EPT = P.EPT;
   constexpr int TL = L / EPT;
+  const int G = a.jgroup;
   cx<R>* ex = reinterpret_cast<cx<R>*>(smem);
-  cx<R>* img = ex + RowLayout<L>::elems(a.lines);
-  const int t = tid % TL, line = tid / TL;
-  const bool act = line < a.lines;
+  cx<R>* img = ex + RowLayout<L>::elems(a.lines * G);
+  const int t = tid % TL, gi = tid / TL, line = gi / G, g = gi % G;
+  const bool member = line < a.lines;
   const int64_t sig0 = bid * a.lines;
   const int64_t sig = sig0 + line;
-  const bool active = act && sig < a.batch;
+  const bool active = member && sig < a.batch;
   const int M1 = a.alpha * L;
   const int64_t nl = min((int64_t)a.lines, a.batch - sig0);
   const cx<R>* src = X + sig0 * a.y_stride;  // y_stride == alpha * L
   for (int64_t i = tid; i < nl * M1; i += nt) img[i] = load_once(src + i);
   __syncthreads();
-  const RowLayout<L> lay(act ? line : 0);
+  const RowLayout<L> lay(member ? gi : 0);
   const cx<R>* im = img + (int64_t)(active ? line : 0) * M1;
   cx<R> acc[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) acc[e] = {(R)0, (R)0};
-  for (int j = 0; j < a.alpha; ++j) {
+  for (int j0 = 0; j0 < a.alpha; j0 += G) {  // uniform over the block
+    const int j = j0 + g;
+    const bool act = member && j < a.alpha;
     cx<R> v[EPT];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) v[e] = active ? cconj(im[a.alpha * (t + TL * e) + j]) : cx<R>{(R)0, (R)0};
+    for (int e = 0; e < EPT; ++e)
+      v[e] = active && act ? cconj(im[a.alpha * (t + TL * e) + j]) : cx<R>{(R)0, (R)0};
     line_fft<R, L, (TL <= 64), single_narrow(L)>(v, t, ex, lay, a.twL, act);
-    if (j == 0) {
+    if (act) {
+      if (j == 0) {
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) acc[e] = cadd(acc[e], v[e]);
-    } else {
-      const cx<R>* __restrict__ pj = a.twPre + j * L + t;  // W_{alpha N}^{j n}
+        for (int e = 0; e < EPT; ++e) acc[e] = cadd(acc[e], v[e]);
+      } else {
+        const cx<R>* __restrict__ pj = a.twPre + j * L + t;  // W_{alpha N}^{j n}
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) acc[e] = cadd(acc[e], cmul(v[e], pj[TL * e]));
+        for (int e = 0; e < EPT; ++e) acc[e] = cadd(acc[e], cmul(v[e], pj[TL * e]));
+      }
     }
   }
-  if (active) {
+  if (G > 1) {  // uniform
+    __syncthreads();  // every group's last transform has read its exchange row
+    if (member) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) ex[lay(t + TL * e)] = acc[e];
+    }
+    __syncthreads();
+    if (active && g == 0) {
+      for (int h = 1; h < G; ++h) {
+        const RowLayout<L> lh(line * G + h);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) acc[e] = cadd(acc[e], lds_read(ex + lh(t + TL * e)));
+      }
+    }
+  }
+  if (active && g == 0) {
     cx<R>* xs = x + sig * a.x_stride;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) store_out(xs + t + TL * e, cscale(cconj(acc[e]), a.scale));

@@ -105,8 +105,8 @@ def test_tune_plan_and_reload(dd, tmp_path):
 
 @pytest.mark.parametrize("N,alpha,batch,code", [(256, 8, 37, 1), (384, 3, 13, 0), (1024, 4, 5, 3)])
 def test_every_one_pass_schedule_round_trips(dd, N, alpha, batch, code):
-    # the inverse runs one thread group per signal whatever the forward's
-    # groups; its signals per block follow the schedule
+    # the inverse runs the forward's block shape: each group sums its values
+    # of j, and the groups' partial sums meet in LDS
     import torch
     x = inputs(code, N, batch, 5)
     xd = torch.from_numpy(x).cuda()
