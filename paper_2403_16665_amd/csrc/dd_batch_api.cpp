@@ -93,9 +93,13 @@ dd_status dd::batch_plan_forced(dd_batch_t* out, const dd_desc* descs, int32_t c
     }
   }
 
-  // queue order: largest spectra first, so that their long chains of tasks
-  // start early and the small ones fill the tail
+  // queue order: one-pass signals of 1024 samples and more first (each is
+  // one long task, a block's whole transform; started late, one of them
+  // outlasts the rest of the queue), then the largest spectra, so that their
+  // many tasks start early and the small ones fill the tail
+  const auto long_task = [&](int i) { return sched[i].single && descs[i].N >= 1024; };
   std::stable_sort(b->kitems.begin(), b->kitems.end(), [&](int a, int c) {
+    if (long_task(a) != long_task(c)) return long_task(a);
     return (int64_t)descs[a].alpha * descs[a].N > (int64_t)descs[c].alpha * descs[c].N;
   });
   const int nk = (int)b->kitems.size();
