@@ -128,7 +128,11 @@ dd_status gen_table(dd_plan* p, void** out, int64_t rows, int64_t cols, int64_t 
 }
 
 // Choose N = N1 * N2 for the two-pass schedule: N1 any instantiated length,
-// N2 a power of two >= 2, as balanced as possible (N1 <= N2 on ties).
+// N2 a power of two >= 2, as balanced as possible (N1 <= N2 on ties); for
+// N <= 4096 (signals whose spectra are too large for a one-pass block), N2
+// as close to 256 as the factors allow: short columns and long rows
+// (measured at 2^24 bins: 1024 = 4 x 256 64 us against 98 us for 32 x 32,
+// 640 = 5 x 128 69 us against 159 us for 20 x 32).
 bool factor_two_pass(int64_t N, int rbytes, int64_t* N1, int64_t* N2) {
   int best = 1 << 30;
   bool found = false;
@@ -137,7 +141,8 @@ bool factor_two_pass(int64_t N, int rbytes, int64_t* N1, int64_t* N2) {
     const int64_t n1 = N / n2;
     if (n1 > 4096 || !len_supported((int)n1) || !pass2_len_supported((int)n2)) continue;
     if (lds_pass1((int)n1, geom_pass((int)n1, rbytes).lines, rbytes, 0) > (size_t)LDS_PASS_MAX) continue;
-    int score = std::abs(ilog2(n1) - ilog2(n2)) * 2 + (n1 > n2 ? 1 : 0);
+    int score = N <= 4096 ? std::abs(ilog2(n2) - 8) * 2 + (n2 > 256 ? 1 : 0)
+                          : std::abs(ilog2(n1) - ilog2(n2)) * 2 + (n1 > n2 ? 1 : 0);
     if (n2 < 16) score += 8;  // narrow column tiles store short runs
     if (n2 % geom_pass((int)n1, rbytes).lines != 0) score += 4;  // idle columns in pass 1
     if (score < best) {
@@ -231,18 +236,25 @@ void single_shape(int L, int alpha, bool real, int rbytes, int64_t batch, int* l
 }
 
 // Built-in schedule rules: one pass when the alpha*N spectrum of a signal
-// fits the LDS of one block, else the most balanced two-pass split; tile
-// choices left to configure().
+// takes at most 32 KiB (or N < 256, or no two-pass split exists) and fits
+// the LDS of one block, else the most balanced two-pass split; tile choices
+// left to configure().  Larger spectra leave a one-pass block LDS-bound (one
+// or two blocks per CU): measured at 2^24 bins per launch, two passes took
+// 64-75 us where one pass took 75-181 us (1024 x 8, 512 x 16, 640 x 8,
+// 1280 x 4, 2048 x 8, 3072 x 4), while at 4096 bins one pass stayed ahead
+// (1024 x 4 55 against 67 us, 512 x 8 59 against 66).
 bool default_sched(int64_t N, int alpha, int rbytes, dd_sched* sc) {
   *sc = dd_sched{};
-  if (N <= 4096 && len_supported((int)N) && lds_single((int)N, 1, alpha, rbytes) <= SINGLE_BUDGET) {
+  int64_t N1 = 0, N2 = 0;
+  const bool split = factor_two_pass(N, rbytes, &N1, &N2);
+  const bool small = (int64_t)alpha * N * 2 * rbytes <= 32 * 1024 || N < 256 || !split;
+  if (small && N <= 4096 && len_supported((int)N) && lds_single((int)N, 1, alpha, rbytes) <= SINGLE_BUDGET) {
     sc->passes = 1;
     sc->N1 = N;
     sc->N2 = 1;
     return true;
   }
-  int64_t N1 = 0, N2 = 0;
-  if (!factor_two_pass(N, rbytes, &N1, &N2)) return false;
+  if (!split) return false;
   sc->passes = 2;
   sc->N1 = N1;
   sc->N2 = N2;
