@@ -289,10 +289,14 @@ __device__ __forceinline__ void body_single_groups(const InAcc& x, cx<R>* __rest
   const int t = tid % TL, g = tid / TL;
   const bool member = g < groups;
   const int M1 = a.alpha * L;
+  // the samples pass through the head of the image: one coalesced read of
+  // each, however many groups share the signal (as in body_single)
+  for (int i = tid; i < L; i += nt) img[i] = cscale(x(sig * a.x_stride, (unsigned)i), a.scale);
+  __syncthreads();
   cx<R> xv[EPT];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e)
-    xv[e] = member ? cscale(x(sig * a.x_stride, (unsigned)(t + TL * e)), a.scale) : cx<R>{(R)0, (R)0};
+  for (int e = 0; e < EPT; ++e) xv[e] = member ? lds_read(img + t + TL * e) : cx<R>{(R)0, (R)0};
+  __syncthreads();  // every group holds its samples before any writes its spectrum over them
   const RowLayout<L> lay(member ? g : 0);
   // real samples: only j <= alpha/2 are transformed (as in body_single)
   const bool herm = x.is_real();
