@@ -93,8 +93,10 @@ typedef struct dd_plan *dd_plan_t;
 /* Create a plan for `batch` transforms of length N with integer dense factor
  * alpha and record duration T (seconds; only the T/N output factor depends
  * on it).  Validates the arguments, factors N (radices 2, 3, 4, 5, 8, 16),
- * chooses the kernel schedule (one fused pass when the alpha*N spectrum of a
- * signal fits on chip, otherwise two passes N = N1*N2), allocates and
+ * chooses the kernel schedule (the tuning table's entry for the problem
+ * class if it has one; else one fused pass when the alpha*N spectrum of a
+ * signal takes at most 32 KiB and fits on chip, otherwise two passes
+ * N = N1*N2), allocates and
  * generates the device twiddle tables on the current device, and
  * synchronises once.
  *   out    : receives the plan handle (NULL on failure).
