@@ -15,7 +15,8 @@ Default workload (headline): the metric's own comparison, batched vs plain.
 Inputs are resident in HBM when the timed region starts.  Prints ONE JSON line.
 
 Other workloads (--workload): batch_c64 (the plain kernel alone, with the
-oracle's CPU rate), real_f32, precision (1 x 2^22, alpha 16, c64, FP64 vs
+oracle's CPU rate), short_c64 (8192 x N = 256, alpha 8: one pass, thread
+groups sharing each signal), real_f32, precision (1 x 2^22, alpha 16, c64, FP64 vs
 FP32 twiddles), plain_f64 (1 x 1024, alpha 4, real float64), uneven,
 serving (a full rate sweep), ablation (the FFT of the zero-padded signals),
 inverse and decimated (alpha = 1/p).
@@ -73,6 +74,7 @@ def measured_traffic(workload):
 WORKLOADS = {
     "headline": dict(batch=0, N=0, alpha=0, dt=1e-3, input="uneven batch + plain kernel + serving"),
     "batch_c64": dict(batch=256, N=65536, alpha=8, dt=1e-3, input="complex64"),
+    "short_c64": dict(batch=8192, N=256, alpha=8, dt=1e-3, input="complex64"),
     "real_f32": dict(batch=256, N=65536, alpha=8, dt=1e-3, input="float32 real"),
     "precision": dict(batch=1, N=1 << 22, alpha=16, dt=1e-3, input="complex64"),
     "plain_f64": dict(batch=1, N=1024, alpha=4, dt=1e-3, input="float64"),
@@ -89,6 +91,8 @@ def make_inputs(name, w):
     N, batch, dt = w["N"], w["batch"], w["dt"]
     if name == "batch_c64":
         return np.stack([siggen.tones_complex(g, N, dt) for g in siggen.rngs(1, batch)])
+    if name == "short_c64":
+        return np.stack([siggen.tones_complex(g, N, dt) for g in siggen.rngs(6, batch)])
     if name == "real_f32":
         return np.stack([siggen.tones_real(g, N, dt, w["alpha"])[0] for g in siggen.rngs(7, batch)]).astype(np.float32)
     if name == "precision":
