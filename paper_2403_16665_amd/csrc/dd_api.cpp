@@ -227,9 +227,10 @@ void single_shape(int L, int alpha, bool real, int rbytes, int64_t batch, int* l
   const Shape* pick = nullptr;
   for (const Shape& c : shapes) {
     if (c.score < 0.9 * best) continue;
-    if (!pick || c.block < pick->block || (c.block == pick->block && (c.rounds < pick->rounds ||
-                                                                      (c.rounds == pick->rounds && c.lines > pick->lines))))
-      pick = &c;
+    const bool better = !pick || c.block < pick->block ||
+                        (c.block == pick->block &&
+                         (c.rounds < pick->rounds || (c.rounds == pick->rounds && c.lines > pick->lines)));
+    if (better) pick = &c;
   }
   if (*lines_io <= 0) *lines_io = pick ? pick->lines : 1;
   if (*groups_io <= 0) *groups_io = pick ? pick->groups : 1;
@@ -237,8 +238,8 @@ void single_shape(int L, int alpha, bool real, int rbytes, int64_t batch, int* l
 
 // Built-in schedule rules: one pass when the alpha*N spectrum of a signal
 // takes at most 32 KiB (or N < 256, or no two-pass split exists) and fits
-// the LDS of one block, else the most balanced two-pass split; tile choices
-// left to configure().  Larger spectra leave a one-pass block LDS-bound (one
+// the LDS of one block, else the two-pass split of factor_two_pass; tile
+// choices left to configure().  Larger spectra leave a one-pass block LDS-bound (one
 // or two blocks per CU): measured at 2^24 bins per launch, two passes took
 // 64-75 us where one pass took 75-181 us (1024 x 8, 512 x 16, 640 x 8,
 // 1280 x 4, 2048 x 8, 3072 x 4), while at 4096 bins one pass stayed ahead

@@ -60,8 +60,8 @@ __device__ __forceinline__ void run_single(const BatchItem* __restrict__ items, 
   DenseArgs<float> a = item_args(it);
   a.lines = 1;
   a.twL = as_global(it.twL1);
-  body_single_groups<float, AnyIn<float>, L>(AnyIn<float>{as_global(it.x), it.real}, as_global(it.X), a, sub, it.lines1, BATCH_THREADS,
-                                             smem, tid);
+  body_single_groups<float, AnyIn<float>, L>(AnyIn<float>{as_global(it.x), it.real}, as_global(it.X), a, sub,
+                                             it.lines1, BATCH_THREADS, smem, tid);
 }
 
 template <int L>

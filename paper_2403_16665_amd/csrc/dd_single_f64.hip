@@ -9,6 +9,7 @@ hipError_t launch_single(int L, const LaunchCfg& c, const cx<double>* x, cx<doub
   return launch_single_impl<double, cx<double>>(L, c, x, X, a);
 }
 int single_occupancy(int L, bool real, double /*tag*/, int block, size_t lds) {
-  return real ? single_occupancy_impl<double, double>(L, block, lds) : single_occupancy_impl<double, cx<double>>(L, block, lds);
+  return real ? single_occupancy_impl<double, double>(L, block, lds)
+              : single_occupancy_impl<double, cx<double>>(L, block, lds);
 }
 }  // namespace dd
