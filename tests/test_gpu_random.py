@@ -1,8 +1,9 @@
 """Seeded random sweep: (N, alpha, batch, input dtype, schedule) drawn over
 the supported space -- powers of two and 3 * 2^a, 5 * 2^a lengths, alpha up
-to 17, ragged batches, real and complex input in both precisions, the
-planner's schedule or a random candidate -- each checked on seeded bins
-against the oracle."""
+to 17, ragged batches (up to 40 signals in the wide draws), real and complex
+input in both precisions, the planner's schedule or a random candidate --
+each checked on seeded bins against the oracle (the wide draws also invert
+complex spectra back to their signals)."""
 import numpy as np
 import pytest
 
@@ -57,6 +58,56 @@ def test_random_configuration(oracle_mod, seed):
         full = None if len(bins) == M else spectrum_rms(x[b], T)
         assert_close(X[b][bins], oracle_mod.alpha_dft_bins(x[b], alpha, T, bins), kind, f"{what} signal {b}",
                      full_rms=full)
+
+
+def draw_wide(seed):
+    rng = np.random.default_rng(seed)
+    N = int(rng.choice(LENGTHS))
+    alpha = int(rng.integers(1, 18))
+    while alpha * N > (1 << 22):
+        alpha = max(1, alpha // 2)
+    return rng, N, alpha, int(rng.integers(1, 41)), int(rng.integers(0, 4)), bool(rng.integers(0, 3) > 0)
+
+
+@pytest.mark.parametrize("seed", range(5000, 5200))
+def test_random_wide_batches_and_round_trip(oracle_mod, seed):
+    """As test_random_configuration with up to 40 signals (ragged last
+    blocks of multi-signal one-pass shapes) and, for complex input, the
+    inverse of the plan's own output back to the signal."""
+    import torch
+    import paper_2403_16665_amd as dd
+    rng, N, alpha, batch, code, random_sched = draw_wide(seed)
+    dt = {dd.DD_F32: np.float32, dd.DD_C64: np.complex64, dd.DD_F64: np.float64, dd.DD_C128: np.complex128}[code]
+    if np.issubdtype(dt, np.complexfloating):
+        x = (rng.standard_normal((batch, N)) + 1j * rng.standard_normal((batch, N))).astype(dt)
+    else:
+        x = rng.standard_normal((batch, N)).astype(dt)
+    T = float(rng.uniform(0.1, 10.0))
+    if random_sched:
+        cands = dd.dense_dft_sched_candidates(N, alpha, batch, code)
+        sc = cands[int(rng.integers(0, len(cands)))]
+        plan = dd.dense_dft_plan_sched(N, alpha, T, batch, code, sc)
+    else:
+        plan = dd.dense_dft_plan(N, alpha, T, batch, code)
+    what = (f"seed {seed}: N={N} alpha={alpha} batch={batch} dtype={code} "
+            f"schedule {dd.dense_dft_plan_get_sched(plan)}")
+    Xd = dd.alpha_dft(torch.from_numpy(x).cuda(), alpha, T, plan=plan)
+    X = Xd.cpu().numpy()
+    kind = "f64" if code in (dd.DD_F64, dd.DD_C128) else "f32"
+    M = alpha * N
+    for b in range(batch):
+        bins = siggen.bin_subset(rng, M, 96)
+        full = None if len(bins) == M else spectrum_rms(x[b], T)
+        assert_close(X[b][bins], oracle_mod.alpha_dft_bins(x[b], alpha, T, bins), kind, f"{what} signal {b}",
+                     full_rms=full)
+    if np.issubdtype(dt, np.complexfloating):
+        back = torch.empty((batch, N), dtype=Xd.dtype, device="cuda")
+        dd.dense_dft_exec_inverse(plan, Xd, back)
+        torch.cuda.synchronize()
+        bk = back.cpu().numpy()
+        for b in range(batch):
+            r = np.linalg.norm(bk[b] - x[b]) / np.linalg.norm(x[b])
+            assert r <= (1e-5 if code == dd.DD_C64 else 1e-12), f"{what} signal {b}: inverse round trip {r:.3e}"
 
 
 @pytest.mark.parametrize("seed", range(20))
