@@ -138,6 +138,36 @@ def test_random_batch_mix(oracle_mod, seed):
                      f"seed {seed} item {i}: N={N} alpha={a} dtype={c}", full_rms=full)
 
 
+@pytest.mark.parametrize("seed", range(40))
+def test_random_batch_mix_wide(oracle_mod, seed):
+    """One persistent batch of 1 to 60 random items up to 2^18 samples and
+    2^21 bins (real float32 and complex64, alpha up to 17): sampled bins of
+    every item against the oracle."""
+    import torch
+    import paper_2403_16665_amd as dd
+    rng = np.random.default_rng(7000 + seed)
+    lengths = [n for n in LENGTHS if 16 <= n <= (1 << 18)]
+    items, xs, Xs = [], [], []
+    for _ in range(int(rng.integers(1, 61))):
+        N = int(rng.choice(lengths))
+        alpha = int(rng.integers(1, 18))
+        while alpha * N > (1 << 21):
+            alpha = max(1, alpha // 2)
+        real = bool(rng.integers(0, 2))
+        x = rng.standard_normal(N).astype(np.float32) if real else \
+            (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64)
+        xs.append(torch.from_numpy(x).cuda())
+        Xs.append(torch.zeros(alpha * N, dtype=torch.complex64, device="cuda"))
+        items.append((N, alpha, N * 1e-3, dd.DD_F32 if real else dd.DD_C64, x))
+    torch.cuda.synchronize()
+    dd.dense_dft_exec_many([(N, a, T, c, xs[i], Xs[i]) for i, (N, a, T, c, _) in enumerate(items)])
+    for i, (N, a, T, c, x) in enumerate(items):
+        bins = siggen.bin_subset(rng, a * N, 64)
+        full = None if len(bins) == a * N else spectrum_rms(x, T)
+        assert_close(Xs[i].cpu().numpy()[bins], oracle_mod.alpha_dft_bins(x, a, T, bins), "f32",
+                     f"seed {seed} item {i}/{len(items)}: N={N} alpha={a} dtype={c}", full_rms=full)
+
+
 @pytest.mark.parametrize("seed", range(20))
 def test_random_inverse(oracle_mod, seed):
     """Inverse transforms of random spectra in both precisions, with the
