@@ -23,8 +23,10 @@ def spectra(rng, batch, M, dtype):
     return X.astype(dtype)
 
 
-@pytest.mark.parametrize("N,alpha,batch", [
-    (1, 4, 3), (16, 2, 5), (256, 8, 4), (1024, 4, 2), (3072, 3, 2), (320, 16, 3),   # one pass
+ONE_PASS = [(1, 4, 3), (16, 2, 5), (256, 8, 4), (1024, 4, 2), (3072, 3, 2), (320, 16, 3)]
+
+
+@pytest.mark.parametrize("N,alpha,batch", ONE_PASS + [
     (8192, 4, 2), (65536, 8, 2), (3 * 2 ** 13, 5, 2), (5 * 2 ** 11, 2, 3), (4096, 16, 2)])
 @pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
 def test_inverse_matches_oracle(oracle_mod, N, alpha, batch, dtype):
@@ -34,7 +36,16 @@ def test_inverse_matches_oracle(oracle_mod, N, alpha, batch, dtype):
     M = alpha * N
     T = 0.37 * N
     X = spectra(rng, batch, M, dtype)
-    x = dd.alpha_idft(torch.from_numpy(X).cuda(), alpha, T).cpu().numpy()
+    code = dd.DD_C64 if dtype == np.complex64 else dd.DD_C128
+    plan = None
+    if (N, alpha, batch) in ONE_PASS:
+        # the one-pass schedule wherever it fits (the planner runs spectra
+        # above 32 KiB in two passes)
+        try:
+            plan = dd.dense_dft_plan_sched(N, alpha, T, batch, code, dd.make_sched(passes=1, N1=N, N2=1))
+        except dd.DenseDFTError:
+            plan = None
+    x = dd.alpha_idft(torch.from_numpy(X).cuda(), alpha, T, plan=plan).cpu().numpy()
     kind = "f32" if dtype == np.complex64 else "f64"
     samples = np.arange(N) if N <= 4096 else siggen.bin_subset(rng, N, 512)
     for b in range(batch):

@@ -86,9 +86,11 @@ def test_real_one_pass_every_bin(oracle_mod, N, dtype, kind):
         rng = np.random.default_rng(17 * N + alpha)
         x = rng.standard_normal((3, N)).astype(dtype)
         T = 0.5
-        plan = dd.dense_dft_plan(N, alpha, T, 3, code)
-        if dd.dense_dft_plan_info(plan)[0] != 1:
+        try:  # the one-pass schedule (the planner runs spectra above 32 KiB in two passes)
+            plan = dd.dense_dft_plan_sched(N, alpha, T, 3, code, dd.make_sched(passes=1, N1=N, N2=1))
+        except dd.DenseDFTError:
             continue  # alpha N too large for one pass in this precision
+        assert dd.dense_dft_plan_info(plan)[0] == 1
         X = dd.alpha_dft(torch.from_numpy(x).cuda(), alpha, T, plan=plan).cpu().numpy()
         M = alpha * N
         m = np.arange(M)
